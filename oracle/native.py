@@ -1,0 +1,160 @@
+"""ctypes binding of the tier-1 C++ oracle (relax.cpp).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the package smoke check and the
+benchmark's CPU-baseline leg, never by the product path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "relax.cpp")
+LIB = os.path.join(HERE, "liborc.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile relax.cpp with g++ (FP64, no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-ffp-contract=off", "-std=c++17",
+                               "-fPIC", "-shared", SRC, "-o", tmp])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        dp = C.POINTER(C.c_double)
+        L.orc_create.restype = P
+        L.orc_create.argtypes = [C.c_int64, dp, dp, dp] + [C.c_double] * 7 + [C.c_uint64]
+        L.orc_destroy.argtypes = [P]
+        L.orc_num_edges.restype = C.c_int64
+        L.orc_num_edges.argtypes = [P]
+        L.orc_neighbours.argtypes = [P, C.c_void_p, C.c_void_p]
+        L.orc_set_spins.argtypes = [P, C.c_void_p]
+        L.orc_get_spins.argtypes = [P, C.c_void_p]
+        L.orc_fields.argtypes = [P, dp, C.c_int64] + [C.c_void_p] * 5
+        L.orc_run.restype = C.c_int
+        L.orc_run.argtypes = [P, C.c_int64, dp, C.c_int64, C.c_int64, C.c_void_p,
+                              C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_void_p,
+                              C.c_void_p, C.c_int64]
+        L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_normal_pair.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                      C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _vp(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_vp(c), _vp(k), _vp(o))
+    return o
+
+
+def normal_pair(seed, c0, c1, tag=0):
+    z = np.zeros(2)
+    lib().orc_normal_pair(int(seed), int(c0), int(c1), int(tag), _vp(z))
+    return z
+
+
+class Oracle:
+    """One model instance held by the C++ oracle."""
+
+    def __init__(self, xy, theta, hk, alpha, neighbor_distance, b, c, beta, gamma,
+                 thermal_std=0.0, thermal_seed=0, **_):
+        self.xy = np.ascontiguousarray(xy, dtype=np.float64)
+        self.theta = np.ascontiguousarray(theta, dtype=np.float64)
+        self.hk = np.ascontiguousarray(hk, dtype=np.float64)
+        self.n = len(self.theta)
+        self._h = lib().orc_create(self.n, _dp(self.xy), _dp(self.theta), _dp(self.hk),
+                                   alpha, neighbor_distance, b, c, beta, gamma,
+                                   thermal_std, int(thermal_seed))
+        if not self._h:
+            raise ValueError("oracle: bad instance")
+
+    @classmethod
+    def from_workload(cls, w):
+        return cls(w.xy, w.theta, w.hk, **w.params())
+
+    def close(self):
+        if self._h:
+            lib().orc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_edges(self):
+        return int(lib().orc_num_edges(self._h))
+
+    def neighbours(self):
+        ptr = np.zeros(self.n + 1, dtype=np.int64)
+        idx = np.zeros(max(1, self.num_edges), dtype=np.int32)
+        lib().orc_neighbours(self._h, _vp(ptr), _vp(idx))
+        return ptr, idx[:self.num_edges]
+
+    def set_spins(self, s):
+        s = np.ascontiguousarray(s, dtype=np.int8)
+        lib().orc_set_spins(self._h, _vp(s))
+
+    def spins(self):
+        s = np.zeros(self.n, dtype=np.int8)
+        lib().orc_get_spins(self._h, _vp(s))
+        return s
+
+    def fields(self, H, t):
+        """(h_par, h_perp, scale) for the current spins at step t."""
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        hp, hq, sc = (np.zeros(self.n) for _ in range(3))
+        lib().orc_fields(self._h, _dp(H), int(t), _vp(hp), _vp(hq), None, None, _vp(sc))
+        return hp, hq, sc
+
+    def dipolar_xy(self):
+        hx, hy = np.zeros(self.n), np.zeros(self.n)
+        H = np.zeros(2)
+        lib().orc_fields(self._h, _dp(H), 0, None, None, _vp(hx), _vp(hy), None)
+        return hx, hy
+
+    def run(self, Hs, t_begin=0, t_end=None, log_cap=None, max_flips_per_step=0):
+        """Run steps; returns dict(status, flips (t, j) arrays, per_step, gaps)."""
+        Hs = np.ascontiguousarray(Hs, dtype=np.float64)
+        K = len(Hs)
+        t_end = K if t_end is None else int(t_end)
+        cap = int(log_cap) if log_cap is not None else 4 * self.n * max(1, t_end - t_begin) // 10 + 1024
+        cap = max(cap, 1024)
+        lt = np.zeros(cap, dtype=np.int32)
+        lj = np.zeros(cap, dtype=np.int32)
+        per = np.zeros(max(1, t_end - t_begin), dtype=np.int32)
+        gaps = np.zeros(3)
+        nf = C.c_int64(0)
+        st = lib().orc_run(self._h, K, _dp(Hs), int(t_begin), t_end, _vp(lt), _vp(lj),
+                           cap, C.byref(nf), _vp(per), _vp(gaps), int(max_flips_per_step))
+        n = nf.value
+        return dict(status=int(st), n_flips=n, step=lt[:min(n, cap)].copy(),
+                    idx=lj[:min(n, cap)].copy(), truncated=n > cap,
+                    per_step=per[:t_end - t_begin].copy(),
+                    gaps=dict(top2_rel=gaps[0], thresh_rel=gaps[1], par_rel=gaps[2]))
