@@ -1,0 +1,197 @@
+/*
+ * asi.h -- C ABI of the MI355X (gfx950) artificial-spin-ice relaxation library.
+ *
+ * The library runs the flatspin dipole model (Jensen et al., "flatspin: A
+ * Large-Scale Artificial Spin Ice Simulator") on the GPU:
+ *   - dipole-dipole field on every magnet from its neighbours within the
+ *     neighbour distance (Sec. II.C, Eq. 3), projected on each magnet's easy
+ *     (parallel) and hard (perpendicular) axis, plus the global applied field
+ *     (Sec. II.D) and a per-step thermal field (Sec. II.E) -- Eq. 2;
+ *   - the generalized Stoner-Wohlfarth switching test (Sec. II.F, Eq. 5 and
+ *     Eq. 6) with per-magnet coercive fields h_k (Sec. II.G);
+ *   - deterministic single-spin-flip relaxation (Sec. II.H): flip the
+ *     flippable magnet with the greatest Eq. 5 left-hand side (ties: lowest
+ *     index), update its neighbours, repeat until none can flip, then take
+ *     the next field step.
+ * All model arithmetic is FP64.  Spins are int8 (+1 / -1).
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an asi_status; nothing throws across the ABI.
+ *     asi_last_error() describes the last failure on the calling thread.
+ *   - Input arrays are copied before the call returns; the caller keeps
+ *     ownership and may free them at once.  Output arrays are allocated by
+ *     the caller, host memory, with the element counts stated below.
+ *   - A handle owns all of its device memory and uses one HIP stream.  Calls
+ *     that return results synchronise that stream first.  A handle is not
+ *     thread-safe; distinct handles may be driven from distinct threads.
+ *   - After a HIP error (ASI_EDEVICE) the handle is poisoned: later calls on
+ *     it return ASI_ESTATE; only asi_destroy remains valid.
+ *   - Positions are in units of the lattice spacing, angles in radians.
+ */
+#ifndef ASI_H
+#define ASI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct asi_sim* asi_handle;
+
+typedef enum {
+  ASI_OK = 0,
+  ASI_EINVAL = -1,   /* bad argument, coincident magnets, step out of range */
+  ASI_ENOMEM = -2,   /* allocation failed or HBM budget exceeded            */
+  ASI_EDEVICE = -3,  /* HIP runtime error; the handle is poisoned            */
+  ASI_ESTATE = -4,   /* handle poisoned, or call invalid in this state       */
+  ASI_ELOOP = -5,    /* a relax exceeded max_flips_per_step                  */
+  ASI_EBUSY = -6     /* server: job not finished yet                         */
+} asi_status;
+
+/* Device memory and stream plumbing.  With alloc == NULL the library uses
+ * hipMalloc / hipFree itself.  With callbacks, every device allocation of
+ * the handle goes through them (for example PyTorch's caching allocator),
+ * stream-ordered on `stream`.  stream == NULL: the library creates its own
+ * (default priority) stream. */
+typedef struct {
+  void* stream;                                            /* hipStream_t */
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);   /* NULL on failure */
+  void (*free)(void* ptr, void* stream, void* ctx);
+  void* ctx;
+} asi_device;
+
+/* One simulation instance (Sec. II).  struct_size = sizeof(asi_params). */
+typedef struct {
+  uint32_t struct_size;
+  int64_t n;                 /* magnets, 1 <= n < 2^31                          */
+  const double* xy;          /* [2n] positions (x0, y0, x1, y1, ...), distinct  */
+  const double* theta;       /* [n] island rotation: mhat = (cos, sin)(theta)   */
+  const int8_t* spin0;       /* [n] start spins +-1, or NULL => all +1          */
+  const double* hk;          /* [n] coercive field h_k^(i) > 0 (Sec. II.G)      */
+  double alpha;              /* dipolar coupling strength of Eq. 3, finite      */
+  double neighbor_distance;  /* d >= 0: j is a neighbour of i iff
+                                (x_i-x_j)^2 + (y_i-y_j)^2 <= (d + 1e-9)^2      */
+  double b, c, beta, gamma;  /* generalized astroid of Eq. 5, all > 0           */
+  double thermal_std;        /* sigma_th >= 0 of Sec. II.E; 0 => no thermal     */
+  uint64_t thermal_seed;     /* Philox4x32-10 key (lo, hi 32 bits)              */
+  int64_t max_flips_per_step;/* 0 => 64 * n; a relax exceeding it => ASI_ELOOP  */
+  int64_t flip_log_capacity; /* entries kept in the flip log; 0 => 4n + 65536.
+                                Flips beyond it are counted and hashed only.    */
+} asi_params;
+
+/* Build an instance: copies the inputs, builds the neighbour lists and the
+ * projected coupling tensors on the device (Sec. II.C).  The current step is
+ * -1 (no applied and no thermal field) until the first asi_run. */
+asi_status asi_create(const asi_params* params, const asi_device* dev, asi_handle* out);
+
+/* Set the external-field time series (Sec. II.D): h_xy[2*k], [2*k+1] is the
+ * global field (x, y) of step k, 0 <= k < n_steps.  Copied. */
+asi_status asi_set_field_protocol(asi_handle h, int64_t n_steps, const double* h_xy);
+
+/* Relax under the current step's fields (Sec. II.H) without advancing t.
+ * flips_out (may be NULL) receives the number of flips of this call. */
+asi_status asi_relax(asi_handle h, int64_t* flips_out);
+
+/* For t = t_begin .. t_end-1: set the fields of step t (applied H[t] and
+ * the thermal draw of step t) and relax.  Requires 0 <= t_begin <= t_end <=
+ * n_steps.  flips_out (may be NULL): flips of this call.  Stops early with
+ * ASI_ELOOP when one step exceeds max_flips_per_step. */
+asi_status asi_run(asi_handle h, int64_t t_begin, int64_t t_end, int64_t* flips_out);
+
+/* Current state: spins [n], total fields projected on the easy axis h_par
+ * [n] and hard axis h_perp [n] as of the end of the last relax, and the
+ * last completed step (-1 if none).  Any pointer may be NULL. */
+asi_status asi_get_state(asi_handle h, int8_t* spins, double* h_par, double* h_perp,
+                         int64_t* step_out);
+
+/* Overwrite the spins [n] (+-1) and the current step (-1 .. n_steps-1),
+ * e.g. to resume from a checkpoint taken at a step boundary.  Fields are
+ * recomputed from the spins on the next relax, so a resumed run is bitwise
+ * identical to an uninterrupted one.  Resets the flip log and its hash. */
+asi_status asi_set_state(asi_handle h, const int8_t* spins, int64_t step);
+
+/* Flip log: the first min(count, cap, flip_log_capacity) flips as
+ * (step, magnet index), the
+ * total number of flips logged since create / set_state, and a running hash
+ * over all of them: hash = 0xcbf29ce484222325, then for each flip
+ * hash = (hash ^ ((uint64)(uint32)step << 32 | (uint32)index)) * 0x100000001b3
+ * modulo 2^64.  step and idx may be NULL when cap == 0. */
+asi_status asi_get_flip_log(asi_handle h, int64_t cap, int32_t* step, int32_t* idx,
+                            int64_t* count_out, uint64_t* hash_out);
+
+/* Per-step flip counts of the protocol's steps [0, n_steps) (counts of the
+ * most recent run of each step).  out: [n_steps] int32. */
+asi_status asi_get_step_flips(asi_handle h, int32_t* out);
+
+/* Evaluate the fields of step t (-1 .. n_steps-1) for the current spins --
+ * one full-field pass over every magnet (Eq. 2, Eq. 3 projected) -- without
+ * relaxing.  Results are read back with asi_get_state. */
+asi_status asi_compute_fields(asi_handle h, int64_t t);
+
+typedef struct {
+  int64_t n;                /* magnets                                          */
+  int64_t n_edges;          /* directed neighbour pairs E                        */
+  int32_t max_degree;       /* padded row length of the neighbour tables         */
+  int32_t relax_waves;      /* wavefronts of the relax workgroup                 */
+  int64_t device_bytes;     /* device memory held by the handle                  */
+  double field_pass_bytes;  /* algorithmic bytes of one full-field pass:
+                               20 per neighbour pair + 53 per magnet            */
+  int64_t flip_log_capacity;/* flip-log entries kept (asi_params)               */
+} asi_info;
+asi_status asi_get_info(asi_handle h, asi_info* out);
+
+/* Kernel timing with HIP events on the handle's stream (off by default).
+ * Totals accumulate from the call that enables timing. */
+typedef struct {
+  int64_t field_launches;   double field_ms;   /* full-field pass kernel */
+  int64_t relax_launches;   double relax_ms;   /* relax kernel           */
+} asi_timing;
+asi_status asi_set_timing(asi_handle h, int32_t enable);
+asi_status asi_get_timing(asi_handle h, asi_timing* out);
+
+asi_status asi_destroy(asi_handle h);
+
+/* Thread-local description of the last failure; valid until the next call
+ * on this thread. */
+const char* asi_last_error(void);
+
+/* ---- batching: many independent instances in one launch per phase -------
+ * Runs every handle from its current step to the end of its own protocol.
+ * All handles must live on the same device; the first handle's stream is
+ * used.  Each instance's flips, spins and fields are bitwise identical to
+ * running it alone with asi_run.  flips_out: [count] or NULL.
+ * use_graph != 0 replays one captured HIP graph per field step. */
+asi_status asi_batch_run(asi_handle* hs, int32_t count, int32_t use_graph, int64_t* flips_out);
+
+/* ---- serving: continuous batching of arriving simulation jobs -----------
+ * A server keeps up to max_slots jobs resident on the device within
+ * hbm_budget_bytes, admitting queued jobs as slots and memory free up.
+ * Each finished job's result is bitwise identical to a plain asi_run of the
+ * same inputs. */
+typedef struct asi_server* asi_server_t;
+asi_status asi_server_create(const asi_device* dev, size_t hbm_budget_bytes,
+                             int32_t max_slots, asi_server_t* out);
+/* Queue a job: instance parameters plus its protocol (copied).  job_id_out
+ * receives a non-negative id.  ASI_ENOMEM if the job alone exceeds the
+ * budget. */
+asi_status asi_server_submit(asi_server_t s, const asi_params* p, int64_t n_steps,
+                             const double* h_xy, int64_t* job_id_out);
+/* Advance the server: admit what fits, run one field step of every resident
+ * job, retire finished ones.  active_out (may be NULL): jobs still queued or
+ * resident. */
+asi_status asi_server_step(asi_server_t s, int32_t* active_out);
+/* done_out = 1 when the job has finished (non-blocking). */
+asi_status asi_server_poll(asi_server_t s, int64_t job_id, int32_t* done_out);
+/* Result of a finished job: spins [n] (may be NULL), flip count and hash,
+ * and host clock seconds at admission and completion.  ASI_EBUSY if not
+ * finished.  The job's memory is released on take. */
+asi_status asi_server_take(asi_server_t s, int64_t job_id, int8_t* spins, int64_t* flips,
+                           uint64_t* flip_hash, double* t_admit, double* t_done);
+asi_status asi_server_destroy(asi_server_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASI_H */

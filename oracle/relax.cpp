@@ -199,8 +199,9 @@ struct StepFields {
   std::vector<double> thx, thy;  // empty when sigma_th == 0
 };
 
+// Step t < 0 is the state before the first field step: no thermal draw.
 void thermal_for_step(const Model& M, int64_t t, StepFields& F) {
-  if (M.sigma_th == 0.0) { F.thx.clear(); F.thy.clear(); return; }
+  if (M.sigma_th == 0.0 || t < 0) { F.thx.clear(); F.thy.clear(); return; }
   F.thx.resize(M.n); F.thy.resize(M.n);
   for (int64_t i = 0; i < M.n; ++i) {
     double z0, z1;

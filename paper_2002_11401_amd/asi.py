@@ -1,0 +1,363 @@
+"""Python binding of the C ABI in include/asi.h (argument marshalling only).
+
+Every step of the model runs in the HIP kernels of libasi.so; this module
+only converts numpy arrays to pointers and status codes to exceptions.
+PyTorch, when used, supplies the HIP stream and the caching allocator for
+the library's device memory.  There is no CPU fallback: without the built
+library, or without a GPU, the calls raise.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes as C
+import os
+import weakref
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libasi.so")
+
+ASI_OK, ASI_EINVAL, ASI_ENOMEM, ASI_EDEVICE, ASI_ESTATE, ASI_ELOOP, ASI_EBUSY = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "ASI_OK", -1: "ASI_EINVAL", -2: "ASI_ENOMEM", -3: "ASI_EDEVICE",
+                -4: "ASI_ESTATE", -5: "ASI_ELOOP", -6: "ASI_EBUSY"}
+FNV_OFFSET = 0xcbf29ce484222325
+FNV_PRIME = 0x100000001b3
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class AsiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class AsiDevice(C.Structure):
+    _fields_ = [("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("ctx", C.c_void_p)]
+
+
+class AsiParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n", C.c_int64), ("xy", C.c_void_p),
+                ("theta", C.c_void_p), ("spin0", C.c_void_p), ("hk", C.c_void_p),
+                ("alpha", C.c_double), ("neighbor_distance", C.c_double),
+                ("b", C.c_double), ("c", C.c_double), ("beta", C.c_double),
+                ("gamma", C.c_double), ("thermal_std", C.c_double),
+                ("thermal_seed", C.c_uint64), ("max_flips_per_step", C.c_int64),
+                ("flip_log_capacity", C.c_int64)]
+
+
+class AsiInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_edges", C.c_int64), ("max_degree", C.c_int32),
+                ("relax_waves", C.c_int32), ("device_bytes", C.c_int64),
+                ("field_pass_bytes", C.c_double), ("flip_log_capacity", C.c_int64)]
+
+
+class AsiTiming(C.Structure):
+    _fields_ = [("field_launches", C.c_int64), ("field_ms", C.c_double),
+                ("relax_launches", C.c_int64), ("relax_ms", C.c_double)]
+
+
+# Every entry point of include/asi.h with its ctypes signature.
+P = C.c_void_p
+I64P = C.POINTER(C.c_int64)
+SIGNATURES = {
+    "asi_create": [C.POINTER(AsiParams), C.POINTER(AsiDevice), C.POINTER(C.c_void_p)],
+    "asi_set_field_protocol": [P, C.c_int64, P],
+    "asi_relax": [P, I64P],
+    "asi_run": [P, C.c_int64, C.c_int64, I64P],
+    "asi_get_state": [P, P, P, P, I64P],
+    "asi_set_state": [P, P, C.c_int64],
+    "asi_get_flip_log": [P, C.c_int64, P, P, I64P, C.POINTER(C.c_uint64)],
+    "asi_get_step_flips": [P, P],
+    "asi_compute_fields": [P, C.c_int64],
+    "asi_get_info": [P, C.POINTER(AsiInfo)],
+    "asi_set_timing": [P, C.c_int32],
+    "asi_get_timing": [P, C.POINTER(AsiTiming)],
+    "asi_destroy": [P],
+    "asi_last_error": [],
+    "asi_batch_run": [P, C.c_int32, C.c_int32, P],
+    "asi_server_create": [C.POINTER(AsiDevice), C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)],
+    "asi_server_submit": [P, C.POINTER(AsiParams), C.c_int64, P, I64P],
+    "asi_server_step": [P, C.POINTER(C.c_int32)],
+    "asi_server_poll": [P, C.c_int64, C.POINTER(C.c_int32)],
+    "asi_server_take": [P, C.c_int64, P, I64P, C.POINTER(C.c_uint64),
+                        C.POINTER(C.c_double), C.POINTER(C.c_double)],
+    "asi_server_destroy": [P],
+}
+
+_lib = None
+
+
+def library():
+    """Load libasi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2002_11401_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_char_p if name == "asi_last_error" else C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != ASI_OK:
+        raise AsiError(st, library().asi_last_error().decode())
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def flip_hash(steps, idx) -> int:
+    """The flip-log hash defined in include/asi.h, for a (step, index) list."""
+    h = FNV_OFFSET
+    for t, j in zip(steps, idx):
+        w = ((int(t) & 0xFFFFFFFF) << 32) | (int(j) & 0xFFFFFFFF)
+        h = ((h ^ w) * FNV_PRIME) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+class _TorchDevice:
+    """asi_device backed by PyTorch's current stream and caching allocator."""
+
+    def __init__(self):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible to PyTorch; the HIP library needs one")
+        self.torch = torch
+        self.dev = torch.cuda.current_device()
+        self.stream = torch.cuda.current_stream()
+        torch_ = torch
+        dev = self.dev
+        stream = self.stream
+
+        def _alloc(nbytes, _st, _ctx):
+            try:
+                return torch_.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+            except Exception:
+                return None
+
+        def _free(p, _st, _ctx):
+            if p:
+                torch_.cuda.caching_allocator_delete(p)
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        self.struct = AsiDevice(C.c_void_p(self.stream.cuda_stream), self._alloc, self._free, None)
+
+
+def make_device(kind: str = "torch"):
+    """'torch': torch stream + caching allocator; 'hip': library-owned stream
+    and hipMalloc."""
+    if kind == "torch":
+        return _TorchDevice()
+    if kind == "hip":
+        class _Plain:
+            struct = AsiDevice(None, ALLOC_FN(), FREE_FN(), None)
+        return _Plain()
+    raise ValueError(kind)
+
+
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for s in list(_live):
+        try:
+            s.close()
+        except Exception:
+            pass
+
+
+def _params(xy, theta, hk, spin0, alpha, neighbor_distance, b, c, beta, gamma,
+            thermal_std=0.0, thermal_seed=0, max_flips_per_step=0, flip_log_capacity=0):
+    keep = [np.ascontiguousarray(xy, dtype=np.float64).reshape(-1),
+            np.ascontiguousarray(theta, dtype=np.float64),
+            np.ascontiguousarray(hk, dtype=np.float64),
+            None if spin0 is None else np.ascontiguousarray(spin0, dtype=np.int8)]
+    n = len(keep[1])
+    if len(keep[0]) != 2 * n or len(keep[2]) != n or (keep[3] is not None and len(keep[3]) != n):
+        raise ValueError("xy must be [n,2]; theta, hk, spin0 must be [n]")
+    p = AsiParams(C.sizeof(AsiParams), n, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[3]),
+                  _ptr(keep[2]), float(alpha), float(neighbor_distance), float(b), float(c),
+                  float(beta), float(gamma), float(thermal_std), int(thermal_seed),
+                  int(max_flips_per_step), int(flip_log_capacity))
+    return p, keep
+
+
+class Sim:
+    """One simulation instance held by the HIP library."""
+
+    def __init__(self, xy, theta, hk, spin0=None, *, alpha, neighbor_distance, b, c, beta,
+                 gamma, thermal_std=0.0, thermal_seed=0, H=None, max_flips_per_step=0,
+                 flip_log_capacity=0, device="torch"):
+        L = library()
+        self._dev = device if not isinstance(device, str) else make_device(device)
+        p, keep = _params(xy, theta, hk, spin0, alpha, neighbor_distance, b, c, beta, gamma,
+                          thermal_std, thermal_seed, max_flips_per_step, flip_log_capacity)
+        h = C.c_void_p()
+        _check(L.asi_create(C.byref(p), C.byref(self._dev.struct), C.byref(h)))
+        self._h = h
+        self.n = len(keep[1])
+        self.K = 0
+        _live.add(self)
+        if H is not None:
+            self.set_protocol(H)
+
+    @classmethod
+    def from_workload(cls, w, device="torch", **kw):
+        return cls(w.xy, w.theta, w.hk, w.spin0, H=w.H, device=device, **w.params(), **kw)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise AsiError(ASI_ESTATE, "closed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().asi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_protocol(self, H):
+        H = np.ascontiguousarray(H, dtype=np.float64).reshape(-1, 2)
+        _check(library().asi_set_field_protocol(self.handle, len(H), _ptr(H)))
+        self.K = len(H)
+
+    def run(self, t_begin=0, t_end=None) -> int:
+        t_end = self.K if t_end is None else int(t_end)
+        f = C.c_int64(0)
+        _check(library().asi_run(self.handle, int(t_begin), t_end, C.byref(f)))
+        return f.value
+
+    def relax(self) -> int:
+        f = C.c_int64(0)
+        _check(library().asi_relax(self.handle, C.byref(f)))
+        return f.value
+
+    def compute_fields(self, t: int):
+        _check(library().asi_compute_fields(self.handle, int(t)))
+
+    def state(self):
+        s = np.zeros(self.n, dtype=np.int8)
+        hp = np.zeros(self.n)
+        hq = np.zeros(self.n)
+        step = C.c_int64(0)
+        _check(library().asi_get_state(self.handle, _ptr(s), _ptr(hp), _ptr(hq), C.byref(step)))
+        return s, hp, hq, step.value
+
+    def set_state(self, spins, step: int):
+        s = np.ascontiguousarray(spins, dtype=np.int8)
+        if len(s) != self.n:
+            raise ValueError("spins must have n entries")
+        _check(library().asi_set_state(self.handle, _ptr(s), int(step)))
+
+    def flip_log(self, cap: Optional[int] = None):
+        cnt = C.c_int64(0)
+        h = C.c_uint64(0)
+        _check(library().asi_get_flip_log(self.handle, 0, None, None, C.byref(cnt), C.byref(h)))
+        m = cnt.value if cap is None else min(cap, cnt.value)
+        st = np.zeros(max(m, 1), dtype=np.int32)
+        ix = np.zeros(max(m, 1), dtype=np.int32)
+        _check(library().asi_get_flip_log(self.handle, m, _ptr(st), _ptr(ix), C.byref(cnt),
+                                          C.byref(h)))
+        got = min(m, cnt.value, self.info()["flip_log_capacity"])
+        return dict(step=st[:got].copy(), idx=ix[:got].copy(), count=cnt.value, hash=h.value)
+
+    def step_flips(self):
+        out = np.zeros(max(self.K, 1), dtype=np.int32)
+        _check(library().asi_get_step_flips(self.handle, _ptr(out)))
+        return out[:self.K]
+
+    def info(self):
+        i = AsiInfo()
+        _check(library().asi_get_info(self.handle, C.byref(i)))
+        return dict(n=i.n, n_edges=i.n_edges, max_degree=i.max_degree,
+                    relax_waves=i.relax_waves, device_bytes=i.device_bytes,
+                    field_pass_bytes=i.field_pass_bytes,
+                    flip_log_capacity=i.flip_log_capacity)
+
+    def set_timing(self, on: bool = True):
+        _check(library().asi_set_timing(self.handle, 1 if on else 0))
+
+    def timing(self):
+        t = AsiTiming()
+        _check(library().asi_get_timing(self.handle, C.byref(t)))
+        return dict(field_launches=t.field_launches, field_ms=t.field_ms,
+                    relax_launches=t.relax_launches, relax_ms=t.relax_ms)
+
+
+def batch_run(sims: Sequence[Sim], use_graph: bool = True):
+    """Run every instance to the end of its own protocol in batched launches."""
+    arr = (C.c_void_p * len(sims))(*[s.handle.value for s in sims])
+    flips = np.zeros(len(sims), dtype=np.int64)
+    _check(library().asi_batch_run(arr, len(sims), 1 if use_graph else 0, _ptr(flips)))
+    return flips
+
+
+class Server:
+    """Continuous-batching server of simulation jobs (device-resident)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int, device="hip"):
+        self._dev = device if not isinstance(device, str) else make_device(device)
+        h = C.c_void_p()
+        _check(library().asi_server_create(C.byref(self._dev.struct), int(hbm_budget_bytes),
+                                           int(max_slots), C.byref(h)))
+        self._h = h
+        self._n = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().asi_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, w, **kw) -> int:
+        p, keep = _params(w.xy, w.theta, w.hk, w.spin0, **w.params(), **kw)
+        H = np.ascontiguousarray(w.H, dtype=np.float64).reshape(-1, 2)
+        jid = C.c_int64(0)
+        _check(library().asi_server_submit(self._h, C.byref(p), len(H), _ptr(H), C.byref(jid)))
+        self._n[jid.value] = len(keep[1])
+        return jid.value
+
+    def step(self) -> int:
+        a = C.c_int32(0)
+        _check(library().asi_server_step(self._h, C.byref(a)))
+        return a.value
+
+    def poll(self, jid: int) -> bool:
+        d = C.c_int32(0)
+        _check(library().asi_server_poll(self._h, int(jid), C.byref(d)))
+        return bool(d.value)
+
+    def take(self, jid: int):
+        n = self._n.pop(jid)
+        s = np.zeros(n, dtype=np.int8)
+        f = C.c_int64(0)
+        h = C.c_uint64(0)
+        ta = C.c_double(0)
+        td = C.c_double(0)
+        _check(library().asi_server_take(self._h, int(jid), _ptr(s), C.byref(f), C.byref(h),
+                                         C.byref(ta), C.byref(td)))
+        return dict(spins=s, flips=f.value, hash=h.value, t_admit=ta.value, t_done=td.value)

@@ -1,0 +1,91 @@
+// Internal device-side data layout shared by the kernels and the host runtime
+// of the spin-ice library.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace asi {
+
+// Rows per neighbour-table slice: one row per lane of a wavefront.
+constexpr int kSlice = 64;
+// Rows per block of the full-field pass (4 wavefronts).
+constexpr int kFieldBlock = 256;
+// Most first-level tiles the relax kernel keeps in LDS.  A tile covers
+// 2^l1_shift consecutive magnets (at least 64).
+constexpr int kMaxL1Tiles = 2048;
+// First-level tiles per second-level group (one per lane).
+constexpr int kL2Group = 64;
+// Largest relax workgroup.
+constexpr int kMaxRelaxWaves = 16;
+
+// Per-instance tables and state; device pointers.  One entry per instance
+// in a device array, so a single launch can serve many instances.
+struct InstDev {
+  int64_t n;              // magnets
+  int32_t D;              // padded row length of the neighbour tables
+  int32_t l1_shift;       // log2 of the first-level tile size of the relax tree
+  // Neighbour tables, sliced: slot k of row i lives at
+  //   ((i / 64) * D + k) * 64 + (i % 64);  col == -1 pads a row.
+  const int32_t* len;     // [n] neighbours of each row
+  const int32_t* col;     // neighbour index j (ascending within a row)
+  const double* A;        // mhat_i    . c_ij  (symmetric: A_ij == A_ji)
+  const double* B;        // mhatperp_i. c_ij  (field at row i from j)
+  const double* Br;       // mhatperp_j. c_ji  (field at neighbour j from row i)
+  const double* mx;       // [n] easy axis mhat_i = (mx, my)
+  const double* my;
+  const double* hk;       // [n] coercive field h_k^(i)
+  double b, c;            // astroid width parameters
+  double e_par, e_perp;   // astroid exponents 2/gamma and 2/beta
+  double sigma;           // thermal std
+  uint64_t seed;          // thermal Philox key
+  const double* H;        // [K][2] applied field per step
+  int64_t K;
+  // mutable state
+  int8_t* s;              // [n] spins
+  double* hd_par;         // [n] dipolar field at step start, canonical order
+  double* hd_perp;
+  double* h_par;          // [n] total field (dipolar + applied + thermal)
+  double* h_perp;
+  double* key;            // [n] Eq. 5 LHS if flippable, else 0
+  double* t1key;          // [ceil(n/64)] per-64-row maximum key
+  uint32_t* t1idx;        //   its index, bit 31 set when that spin is -1
+  int32_t* log_t;         // flip log
+  int32_t* log_j;
+  int64_t log_cap;
+  int32_t* step_flips;    // [K] flips of each step (may be null)
+  int64_t max_flips;      // per relax
+};
+
+// Per-instance run cursor, device-resident so captured graphs can replay the
+// same launches step after step.
+struct RunDev {
+  int64_t t;          // step the next field pass evaluates (-1: no field)
+  int64_t t_end;      // run stops before this step
+  int32_t active;     // instance takes part in the next launch
+  int32_t status;     // 0, or ASI_ELOOP
+  int64_t flips;      // flips since create / set_state
+  int64_t flips_call; // flips since the host last cleared it
+  uint64_t hash;      // running flip-log hash
+  int64_t cur_step;   // last relaxed step
+};
+
+void launch_neighbour_count(const double* x, const double* y, const int32_t* cellx,
+                            const int32_t* celly, const int32_t* cell_start,
+                            const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,
+                            double cut2, int32_t* len, int32_t* dup_flag, hipStream_t st);
+void launch_neighbour_fill(const double* x, const double* y, const double* mx, const double* my,
+                           const int32_t* cellx, const int32_t* celly, const int32_t* cell_start,
+                           const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,
+                           double cut2, double alpha, int32_t D, int32_t* col, double* A,
+                           double* B, double* Br, hipStream_t st);
+void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,
+                  const int32_t* blk_row0, int64_t nblocks, hipStream_t st);
+void launch_relax(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
+                  size_t lds_bytes, hipStream_t st);
+void launch_set_run(RunDev* run, int64_t t, int64_t t_end, int32_t active, int32_t reset_log,
+                    int64_t cur_step, hipStream_t st);
+size_t relax_lds_bytes(int64_t n, int32_t l1_shift);
+int32_t relax_l1_shift(int64_t n);
+
+}  // namespace asi

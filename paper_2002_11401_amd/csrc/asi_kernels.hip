@@ -1,0 +1,627 @@
+// HIP kernels (gfx950) of the spin-ice relaxation path.
+//
+// Model: flatspin dipole model (Jensen et al.), Sec. II.  All field and
+// margin arithmetic is FP64 and this file is compiled without FMA
+// contraction, so every kernel that evaluates the same expression on the
+// same inputs produces the same bits -- plain, batched and served runs agree
+// bitwise by construction.
+//
+//   k_nb_count / k_nb_fill  neighbour tables of Sec. II.C and the projected
+//                           couplings of Eq. 3 (once per instance)
+//   k_field                 full-field pass: Eq. 3 gathered in ascending
+//                           neighbour order, plus applied field (Sec. II.D)
+//                           and thermal field (Sec. II.E), Eq. 2, projected;
+//                           switching key of Eq. 5 / Eq. 6; per-64-row maxima
+//   k_relax                 one workgroup per instance: argmax over the
+//                           flippable keys (ties: lowest index), flip, update
+//                           the neighbours' fields incrementally, repeat
+//                           until none can flip (Sec. II.H)
+#include <climits>
+
+#include "asi_internal.h"
+
+namespace asi {
+namespace {
+
+// ------------------------------------------------------------ Philox4x32-10
+// Counter-based generator of Salmon et al. (SC'11): ten rounds; each round
+// multiplies counter words 0 and 2 by the two round multipliers and xors the
+// high halves into words 1 and 3 with the key; the key advances by the two
+// Weyl increments between rounds.
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+  }
+  return c;
+}
+
+// Thermal field of Sec. II.E: two independent N(0,1) draws for magnet i at
+// step t (counter (i, t, 0, 0)), by Box-Muller on 53-bit uniforms
+// u1 in (0, 1] and u2 in [0, 1).
+__device__ inline void thermal_normals(uint64_t seed, uint32_t i, uint32_t t, double& z0,
+                                       double& z1) {
+  const U4 o = philox4x32_10(U4{i, t, 0u, 0u}, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t a = ((((uint64_t)o.x) << 32) | o.y) >> 11;
+  const uint64_t b = ((((uint64_t)o.z) << 32) | o.w) >> 11;
+  const double u1 = (double)(a + 1) * 0x1p-53;
+  const double u2 = (double)b * 0x1p-53;
+  const double rad = sqrt(-2.0 * log(u1));
+  const double ang = 6.283185307179586 * u2;
+  double sn, cs;
+  sincos(ang, &sn, &cs);
+  z0 = rad * cs;
+  z1 = rad * sn;
+}
+
+// Switching key: the left-hand side of Eq. 5 when magnet i may flip, i.e.
+// the field opposes the moment (Eq. 6, s_i h_par < 0) and Eq. 5 exceeds 1;
+// otherwise 0.  Exponents ep = 2/gamma, eq = 2/beta.
+__device__ inline double switching_key(int s, double hp, double hq, double hk, double b,
+                                       double c, double ep, double eq) {
+  const bool against = (s > 0) ? (hp < 0.0) : (hp > 0.0);
+  if (!against) return 0.0;
+  const double a = fabs(hp) / (b * hk);
+  const double q = fabs(hq) / (c * hk);
+  const double L = pow(a, ep) + pow(q, eq);
+  return (L > 1.0) ? L : 0.0;
+}
+
+// Eq. 3 for a unit source moment mhat_s at (sx, sy) seen at (fx, fy),
+// projected on the observer's easy axis (A) and hard axis (B);
+// mhatperp = (-my, mx).  A is symmetric in (f, s) bit for bit: swapping
+// the two negates r, which negates both dot products of the 3(.)(.) term.
+__device__ inline void coupling(double fx, double fy, double fmx, double fmy, double sx,
+                                double sy, double smx, double smy, double alpha, double& A,
+                                double& B) {
+  const double rx = fx - sx;
+  const double ry = fy - sy;
+  const double r2 = rx * rx + ry * ry;
+  const double r = sqrt(r2);
+  const double inv3 = 1.0 / (r2 * r);
+  const double inv5 = inv3 / r2;
+  const double af = fmx * rx + fmy * ry;
+  const double as = smx * rx + smy * ry;
+  const double pf = fmx * ry - fmy * rx;
+  const double mm = fmx * smx + fmy * smy;
+  const double pm = fmx * smy - fmy * smx;
+  A = alpha * (3.0 * (af * as) * inv5 - mm * inv3);
+  B = alpha * (3.0 * (pf * as) * inv5 - pm * inv3);
+}
+
+// Wave-wide argmax of (key, payload) where lane order is index order:
+// largest key, and among equal keys the lowest lane.  All 64 lanes call.
+__device__ inline void wave_argmax(double& key, uint32_t& payload) {
+  double m = key;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  const unsigned long long bal = __ballot(key == m);
+  const int src = __ffsll((unsigned long long)bal) - 1;
+  payload = __shfl(payload, src, 64);
+  key = m;
+}
+
+__device__ inline int64_t slot_of(int64_t i, int32_t D, int32_t k) {
+  return ((i >> 6) * (int64_t)D + k) * kSlice + (i & (kSlice - 1));
+}
+
+// ------------------------------------------------------------ neighbours
+// Cells of side >= the cutoff, magnets sorted by cell (ascending index
+// within a cell); a magnet's neighbours lie in its 3 x 3 cell block.
+__global__ void k_nb_count(const double* __restrict__ x, const double* __restrict__ y,
+                           const int32_t* __restrict__ cellx, const int32_t* __restrict__ celly,
+                           const int32_t* __restrict__ cstart, const int32_t* __restrict__ cmem,
+                           int64_t n, int64_t gx, int64_t gy, double cut2,
+                           int32_t* __restrict__ len, int32_t* __restrict__ dup) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], yi = y[i];
+  const int64_t cx = cellx[i], cy = celly[i];
+  int32_t cnt = 0;
+  for (int64_t yy = cy - 1; yy <= cy + 1; ++yy) {
+    if (yy < 0 || yy >= gy) continue;
+    for (int64_t xx = cx - 1; xx <= cx + 1; ++xx) {
+      if (xx < 0 || xx >= gx) continue;
+      const int64_t c = yy * gx + xx;
+      for (int32_t p = cstart[c]; p < cstart[c + 1]; ++p) {
+        const int32_t j = cmem[p];
+        if (j == i) continue;
+        const double dx = xi - x[j];
+        const double dy = yi - y[j];
+        const double r2 = dx * dx + dy * dy;
+        if (r2 <= cut2) {
+          ++cnt;
+          if (r2 == 0.0) *dup = 1;
+        }
+      }
+    }
+  }
+  len[i] = cnt;
+}
+
+// Fills row i in ascending neighbour order by a 9-way merge of the
+// (ascending) member lists of its 3 x 3 cell block, and computes the
+// projected couplings of each pair.
+__global__ void k_nb_fill(const double* __restrict__ x, const double* __restrict__ y,
+                          const double* __restrict__ mx, const double* __restrict__ my,
+                          const int32_t* __restrict__ cellx, const int32_t* __restrict__ celly,
+                          const int32_t* __restrict__ cstart, const int32_t* __restrict__ cmem,
+                          int64_t n, int64_t gx, int64_t gy, double cut2, double alpha,
+                          int32_t D, int32_t* __restrict__ col, double* __restrict__ A,
+                          double* __restrict__ B, double* __restrict__ Br) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double xi = x[i], yi = y[i], mxi = mx[i], myi = my[i];
+  const int64_t cx = cellx[i], cy = celly[i];
+  int32_t pos[9], end[9], head[9];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    const int64_t xx = cx + (r % 3) - 1;
+    const int64_t yy = cy + (r / 3) - 1;
+    const bool ok = xx >= 0 && xx < gx && yy >= 0 && yy < gy;
+    const int64_t c = yy * gx + xx;
+    pos[r] = ok ? cstart[c] : 0;
+    end[r] = ok ? cstart[c + 1] : 0;
+    head[r] = pos[r] < end[r] ? cmem[pos[r]] : INT_MAX;
+  }
+  int32_t k = 0;
+  while (true) {
+    int32_t best = INT_MAX;
+    int br = -1;
+#pragma unroll
+    for (int r = 0; r < 9; ++r)
+      if (head[r] < best) {
+        best = head[r];
+        br = r;
+      }
+    if (br < 0) break;
+#pragma unroll
+    for (int r = 0; r < 9; ++r)
+      if (r == br) {
+        ++pos[r];
+        head[r] = pos[r] < end[r] ? cmem[pos[r]] : INT_MAX;
+      }
+    const int32_t j = best;
+    if (j == i) continue;
+    const double xj = x[j], yj = y[j];
+    const double dx = xi - xj;
+    const double dy = yi - yj;
+    if (dx * dx + dy * dy > cut2) continue;
+    if (k >= D) break;  // cannot happen: D is the maximum count
+    double a, b, ar, bt;
+    const double mxj = mx[j], myj = my[j];
+    coupling(xi, yi, mxi, myi, xj, yj, mxj, myj, alpha, a, b);
+    coupling(xj, yj, mxj, myj, xi, yi, mxi, myi, alpha, ar, bt);
+    const int64_t sl = slot_of(i, D, k);
+    col[sl] = j;
+    A[sl] = a;
+    B[sl] = b;
+    Br[sl] = bt;
+    ++k;
+  }
+  for (; k < D; ++k) {
+    const int64_t sl = slot_of(i, D, k);
+    col[sl] = -1;
+    A[sl] = 0.0;
+    B[sl] = 0.0;
+    Br[sl] = 0.0;
+  }
+}
+
+// ------------------------------------------------------------ full-field pass
+// One lane per magnet.  Dipolar sum of Eq. 3 over the neighbours in
+// ascending order (one accumulator per axis, left to right), then
+// h = h_dip + H[t] + h_th projected (Eq. 2), then the switching key.
+// Each wavefront also writes the maximum key of its 64 rows.
+__global__ __launch_bounds__(kFieldBlock) void k_field(const InstDev* __restrict__ insts,
+                                                      RunDev* __restrict__ runs,
+                                                      const int32_t* __restrict__ blk_inst,
+                                                      const int32_t* __restrict__ blk_row0) {
+  const int q = blk_inst[blockIdx.x];
+  const RunDev* R = runs + q;
+  if (!R->active) return;
+  const InstDev* I = insts + q;
+  const int64_t n = I->n;
+  const int64_t row0 = blk_row0[blockIdx.x];
+  const int64_t i = row0 + threadIdx.x;
+  const int64_t wave_row0 = row0 + (threadIdx.x & ~63);
+  if (wave_row0 >= n) return;  // whole wavefront past the end
+  const int64_t t = R->t;
+  const int32_t D = I->D;
+  const int8_t* __restrict__ s = I->s;
+
+  double key = 0.0;
+  uint32_t payload = 0;
+  if (i < n) {
+    const int32_t L = I->len[i];
+    const int64_t base = slot_of(i, D, 0);
+    const int32_t* __restrict__ col = I->col + base;
+    const double* __restrict__ A = I->A + base;
+    const double* __restrict__ B = I->B + base;
+    double p = 0.0, pq = 0.0;
+    int32_t k = 0;
+    for (; k + 4 <= L; k += 4) {
+      const int32_t j0 = col[(k + 0) * kSlice], j1 = col[(k + 1) * kSlice];
+      const int32_t j2 = col[(k + 2) * kSlice], j3 = col[(k + 3) * kSlice];
+      const double a0 = A[(k + 0) * kSlice], a1 = A[(k + 1) * kSlice];
+      const double a2 = A[(k + 2) * kSlice], a3 = A[(k + 3) * kSlice];
+      const double b0 = B[(k + 0) * kSlice], b1 = B[(k + 1) * kSlice];
+      const double b2 = B[(k + 2) * kSlice], b3 = B[(k + 3) * kSlice];
+      const int s0 = s[j0], s1 = s[j1], s2 = s[j2], s3 = s[j3];
+      p += (s0 > 0) ? a0 : -a0;
+      pq += (s0 > 0) ? b0 : -b0;
+      p += (s1 > 0) ? a1 : -a1;
+      pq += (s1 > 0) ? b1 : -b1;
+      p += (s2 > 0) ? a2 : -a2;
+      pq += (s2 > 0) ? b2 : -b2;
+      p += (s3 > 0) ? a3 : -a3;
+      pq += (s3 > 0) ? b3 : -b3;
+    }
+    for (; k < L; ++k) {
+      const int32_t j = col[k * kSlice];
+      const double a = A[k * kSlice], b = B[k * kSlice];
+      const int sj = s[j];
+      p += (sj > 0) ? a : -a;
+      pq += (sj > 0) ? b : -b;
+    }
+    I->hd_par[i] = p;
+    I->hd_perp[i] = pq;
+    const double mxi = I->mx[i], myi = I->my[i];
+    double hp = p, hq = pq;
+    if (t >= 0) {
+      const double Hx = I->H[2 * t], Hy = I->H[2 * t + 1];
+      hp = hp + (Hx * mxi + Hy * myi);
+      hq = hq + (Hy * mxi - Hx * myi);
+      if (I->sigma > 0.0) {
+        double z0, z1;
+        thermal_normals(I->seed, (uint32_t)i, (uint32_t)t, z0, z1);
+        const double tx = I->sigma * z0, ty = I->sigma * z1;
+        hp = hp + (tx * mxi + ty * myi);
+        hq = hq + (ty * mxi - tx * myi);
+      }
+    }
+    I->h_par[i] = hp;
+    I->h_perp[i] = hq;
+    const int si = s[i];
+    key = switching_key(si, hp, hq, I->hk[i], I->b, I->c, I->e_par, I->e_perp);
+    I->key[i] = key;
+    payload = (uint32_t)i | (si < 0 ? 0x80000000u : 0u);
+  }
+  wave_argmax(key, payload);
+  if ((threadIdx.x & 63) == 0) {
+    I->t1key[wave_row0 >> 6] = key;
+    I->t1idx[wave_row0 >> 6] = payload;
+  }
+}
+
+// ------------------------------------------------------------ relax
+struct RelaxLds {
+  double* l1k;
+  uint32_t* l1i;
+  int32_t* l1flag;
+  int32_t* l1list;
+  double* l2k;
+  uint32_t* l2i;
+  int32_t* l2flag;
+  int32_t* l2list;
+};
+
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+__device__ inline RelaxLds carve(unsigned char* base, int nt1, int nt2) {
+  RelaxLds L;
+  size_t off = 0;
+  L.l1k = (double*)(base + off);
+  off = align16(off + sizeof(double) * nt1);
+  L.l1i = (uint32_t*)(base + off);
+  off = align16(off + sizeof(uint32_t) * nt1);
+  L.l1flag = (int32_t*)(base + off);
+  off = align16(off + sizeof(int32_t) * nt1);
+  L.l1list = (int32_t*)(base + off);
+  off = align16(off + sizeof(int32_t) * nt1);
+  L.l2k = (double*)(base + off);
+  off = align16(off + sizeof(double) * nt2);
+  L.l2i = (uint32_t*)(base + off);
+  off = align16(off + sizeof(uint32_t) * nt2);
+  L.l2flag = (int32_t*)(base + off);
+  off = align16(off + sizeof(int32_t) * nt2);
+  L.l2list = (int32_t*)(base + off);
+  return L;
+}
+
+// One workgroup relaxes one instance at its current step.  The flippable
+// keys are kept in a three-level max tree: the key array in HBM, first-level
+// tiles of 2^l1_shift magnets and second-level groups of 64 tiles in LDS.
+// Per flip: the root gives j; thread 0 flips it and logs it; every thread
+// updates some of j's neighbours (fields += 2 s_new * coupling, new key);
+// the touched tiles and groups are rescanned.
+__global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __restrict__ insts,
+                                                              RunDev* __restrict__ runs) {
+  RunDev* R = runs + blockIdx.x;
+  if (!R->active) return;
+  const InstDev* I = insts + blockIdx.x;
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ int sh_n1, sh_n2;
+  __shared__ double sh_key;
+  __shared__ uint32_t sh_pay;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int NT = blockDim.x, NW = NT >> 6;
+  const int64_t n = I->n;
+  const int l1s = I->l1_shift;
+  const int nt1 = (int)((n + (1LL << l1s) - 1) >> l1s);
+  const int nt2 = (nt1 + kL2Group - 1) / kL2Group;
+  const int64_t nt0 = (n + 63) >> 6;
+  const int per0 = 1 << (l1s - 6);  // per-64-row maxima in one tile
+  const int seg = 1 << (l1s - 6);   // magnets per lane in a tile rescan
+  RelaxLds L = carve(lds_raw, nt1, nt2);
+
+  // local copies of the instance description
+  const int32_t D = I->D;
+  const int32_t* __restrict__ colp = I->col;
+  const double* __restrict__ Ap = I->A;
+  const double* __restrict__ Brp = I->Br;
+  const double* __restrict__ hkp = I->hk;
+  int8_t* __restrict__ sp = I->s;
+  double* __restrict__ hpp = I->h_par;
+  double* __restrict__ hqp = I->h_perp;
+  double* __restrict__ keyp = I->key;
+  const double pb = I->b, pc = I->c, ep = I->e_par, eq = I->e_perp;
+  const int64_t max_flips = I->max_flips;
+  const int64_t t = R->t;
+
+  // first level from the per-64-row maxima of the field pass
+  for (int e = tid; e < nt1; e += NT) {
+    double bk = 0.0;
+    uint32_t bi = 0;
+    for (int u = 0; u < per0; ++u) {
+      const int64_t f = (int64_t)e * per0 + u;
+      if (f < nt0) {
+        const double k = I->t1key[f];
+        if (k > bk) {
+          bk = k;
+          bi = I->t1idx[f];
+        }
+      }
+    }
+    L.l1k[e] = bk;
+    L.l1i[e] = bi;
+    L.l1flag[e] = 0;
+  }
+  if (tid == 0) {
+    sh_n1 = 0;
+    sh_n2 = 0;
+  }
+  __syncthreads();
+  for (int g = wave; g < nt2; g += NW) {
+    const int e = g * kL2Group + lane;
+    double k = (e < nt1) ? L.l1k[e] : 0.0;
+    uint32_t pay = (e < nt1) ? L.l1i[e] : 0u;
+    wave_argmax(k, pay);
+    if (lane == 0) {
+      L.l2k[g] = k;
+      L.l2i[g] = pay;
+      L.l2flag[g] = 0;
+    }
+  }
+  __syncthreads();
+
+  int64_t flips = 0;
+  int64_t logpos = R->flips;
+  uint64_t hash = R->hash;
+  int status = 0;
+  const int per2 = (nt2 + 63) >> 6;
+
+  while (true) {
+    if (wave == 0) {
+      double bk = 0.0;
+      uint32_t bp = 0;
+      for (int u = 0; u < per2; ++u) {
+        const int g = lane * per2 + u;
+        if (g < nt2) {
+          const double k = L.l2k[g];
+          if (k > bk) {
+            bk = k;
+            bp = L.l2i[g];
+          }
+        }
+      }
+      wave_argmax(bk, bp);
+      if (lane == 0) {
+        sh_key = bk;
+        sh_pay = bp;
+      }
+    }
+    __syncthreads();
+    const double top = sh_key;
+    const uint32_t pay = sh_pay;
+    if (!(top > 0.0)) break;
+    if (flips >= max_flips) {
+      status = -5;
+      break;
+    }
+    const int64_t j = pay & 0x7fffffffu;
+    const int s_new = (pay & 0x80000000u) ? 1 : -1;
+    if (tid == 0) {
+      sp[j] = (int8_t)s_new;
+      keyp[j] = 0.0;
+      if (logpos < I->log_cap) {
+        I->log_t[logpos] = (int32_t)t;
+        I->log_j[logpos] = (int32_t)j;
+      }
+      const uint64_t w = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)j;
+      hash = (hash ^ w) * 0x100000001b3ull;
+      const int e = (int)(j >> l1s);
+      if (atomicExch(&L.l1flag[e], 1) == 0) L.l1list[atomicAdd(&sh_n1, 1)] = e;
+    }
+    ++logpos;
+    ++flips;
+    const double two = (s_new > 0) ? 2.0 : -2.0;
+    for (int k = tid; k < D; k += NT) {
+      const int64_t sl = slot_of(j, D, k);
+      const int32_t i = colp[sl];
+      if (i >= 0) {
+        const double a = Ap[sl], br = Brp[sl];
+        const double hp = hpp[i] + two * a;
+        const double hq = hqp[i] + two * br;
+        const int si = sp[i];
+        const double kk = switching_key(si, hp, hq, hkp[i], pb, pc, ep, eq);
+        hpp[i] = hp;
+        hqp[i] = hq;
+        keyp[i] = kk;
+        const int e = (int)(i >> l1s);
+        if (atomicExch(&L.l1flag[e], 1) == 0) L.l1list[atomicAdd(&sh_n1, 1)] = e;
+      }
+    }
+    __syncthreads();
+    const int n1 = sh_n1;
+    for (int u = wave; u < n1; u += NW) {
+      const int e = L.l1list[u];
+      const int64_t r0 = ((int64_t)e << l1s) + (int64_t)lane * seg;
+      double bk = 0.0;
+      uint32_t bp = 0;
+      for (int m = 0; m < seg; ++m) {
+        const int64_t ii = r0 + m;
+        if (ii < n) {
+          const double k = keyp[ii];
+          const int si = sp[ii];
+          if (k > bk) {
+            bk = k;
+            bp = (uint32_t)ii | (si < 0 ? 0x80000000u : 0u);
+          }
+        }
+      }
+      wave_argmax(bk, bp);
+      if (lane == 0) {
+        L.l1k[e] = bk;
+        L.l1i[e] = bp;
+        L.l1flag[e] = 0;
+        const int g = e / kL2Group;
+        if (atomicExch(&L.l2flag[g], 1) == 0) L.l2list[atomicAdd(&sh_n2, 1)] = g;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) sh_n1 = 0;
+    const int n2 = sh_n2;
+    for (int u = wave; u < n2; u += NW) {
+      const int g = L.l2list[u];
+      const int e = g * kL2Group + lane;
+      double k = (e < nt1) ? L.l1k[e] : 0.0;
+      uint32_t p2 = (e < nt1) ? L.l1i[e] : 0u;
+      wave_argmax(k, p2);
+      if (lane == 0) {
+        L.l2k[g] = k;
+        L.l2i[g] = p2;
+        L.l2flag[g] = 0;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) sh_n2 = 0;
+  }
+  if (tid == 0) {
+    R->flips += flips;
+    R->flips_call += flips;
+    R->hash = hash;
+    if (t >= 0 && t < I->K && I->step_flips) I->step_flips[t] = (int32_t)flips;
+    R->cur_step = t;
+    R->t = t + 1;
+    if (status != 0) R->status = status;
+    R->active = (status == 0 && R->t < R->t_end) ? 1 : 0;
+  }
+}
+
+// Run-cursor update, launched on the stream so it orders with the kernels
+// (and can sit inside a captured graph).
+__global__ void k_set_run(RunDev* R, int64_t t, int64_t t_end, int32_t active,
+                          int32_t reset_log, int64_t cur_step) {
+  if (threadIdx.x != 0) return;
+  R->t = t;
+  R->t_end = t_end;
+  R->active = active;
+  R->status = 0;
+  R->flips_call = 0;
+  if (reset_log) {
+    R->flips = 0;
+    R->hash = 0xcbf29ce484222325ull;
+    R->cur_step = cur_step;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+void launch_neighbour_count(const double* x, const double* y, const int32_t* cellx,
+                            const int32_t* celly, const int32_t* cell_start,
+                            const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,
+                            double cut2, int32_t* len, int32_t* dup_flag, hipStream_t st) {
+  const int bs = 256;
+  const int64_t nb = (n + bs - 1) / bs;
+  hipLaunchKernelGGL(k_nb_count, dim3((unsigned)nb), dim3(bs), 0, st, x, y, cellx, celly,
+                     cell_start, cell_members, n, gx, gy, cut2, len, dup_flag);
+}
+
+void launch_neighbour_fill(const double* x, const double* y, const double* mx, const double* my,
+                           const int32_t* cellx, const int32_t* celly, const int32_t* cell_start,
+                           const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,
+                           double cut2, double alpha, int32_t D, int32_t* col, double* A,
+                           double* B, double* Br, hipStream_t st) {
+  const int bs = 128;
+  const int64_t nb = (n + bs - 1) / bs;
+  hipLaunchKernelGGL(k_nb_fill, dim3((unsigned)nb), dim3(bs), 0, st, x, y, mx, my, cellx, celly,
+                     cell_start, cell_members, n, gx, gy, cut2, alpha, D, col, A, B, Br);
+}
+
+void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,
+                  const int32_t* blk_row0, int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return;
+  hipLaunchKernelGGL(k_field, dim3((unsigned)nblocks), dim3(kFieldBlock), 0, st, insts, runs,
+                     blk_inst, blk_row0);
+}
+
+void launch_relax(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
+                  size_t lds_bytes, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_relax, dim3((unsigned)count), dim3(64 * waves), lds_bytes, st, insts,
+                     runs);
+}
+
+void launch_set_run(RunDev* run, int64_t t, int64_t t_end, int32_t active, int32_t reset_log,
+                    int64_t cur_step, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_run, dim3(1), dim3(64), 0, st, run, t, t_end, active, reset_log,
+                     cur_step);
+}
+
+int32_t relax_l1_shift(int64_t n) {
+  int32_t s = 6;
+  while (((n + (1LL << s) - 1) >> s) > kMaxL1Tiles) ++s;
+  return s;
+}
+
+size_t relax_lds_bytes(int64_t n, int32_t l1_shift) {
+  const int64_t nt1 = (n + (1LL << l1_shift) - 1) >> l1_shift;
+  const int64_t nt2 = (nt1 + kL2Group - 1) / kL2Group;
+  size_t off = 0;
+  off = align16(off + sizeof(double) * nt1);
+  off = align16(off + sizeof(uint32_t) * nt1);
+  off = align16(off + sizeof(int32_t) * nt1);
+  off = align16(off + sizeof(int32_t) * nt1);
+  off = align16(off + sizeof(double) * nt2);
+  off = align16(off + sizeof(uint32_t) * nt2);
+  off = align16(off + sizeof(int32_t) * nt2);
+  off = align16(off + sizeof(int32_t) * nt2);
+  return off;
+}
+
+}  // namespace asi

@@ -1,0 +1,1090 @@
+// Host runtime behind the C ABI of include/asi.h: argument validation, the
+// cell sort that seeds the device neighbour build, device-memory bridge,
+// per-step launch sequence, batching with captured graphs, and the serving
+// loop.  Every step of the model itself runs in the kernels of
+// asi_kernels.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/asi.h"
+#include "asi_internal.h"
+
+using namespace asi;
+
+namespace {
+
+thread_local std::string g_err;
+
+asi_status fail(asi_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Device memory of one owner (handle or server), through the caller's
+// allocator callbacks or hipMalloc.
+struct DevMem {
+  asi_device dev{};
+  hipStream_t st = nullptr;
+  std::vector<std::pair<void*, size_t>> blocks;
+  size_t total = 0;
+  bool fail_next = false;  // allocation fault injection (ASI_FAIL_ALLOC)
+
+  void* alloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~(size_t)255;
+    void* p = nullptr;
+    if (fail_next) return nullptr;
+    if (dev.alloc) {
+      p = dev.alloc(bytes, (void*)st, dev.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    if (p) {
+      blocks.emplace_back(p, bytes);
+      total += bytes;
+    }
+    return p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    for (size_t k = 0; k < blocks.size(); ++k)
+      if (blocks[k].first == p) {
+        total -= blocks[k].second;
+        if (dev.free)
+          dev.free(p, (void*)st, dev.ctx);
+        else
+          (void)hipFree(p);
+        blocks.erase(blocks.begin() + k);
+        return;
+      }
+  }
+  void release_all() {
+    for (auto& b : blocks) {
+      if (dev.free)
+        dev.free(b.first, (void*)st, dev.ctx);
+      else
+        (void)hipFree(b.first);
+    }
+    blocks.clear();
+    total = 0;
+  }
+};
+
+struct TimerPair {
+  hipEvent_t a, b;
+  int kind;  // 0 field, 1 relax
+};
+
+}  // namespace
+
+struct asi_sim {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevMem mem;
+  int64_t n = 0, E = 0;
+  int32_t D = 0, l1s = 6, relax_waves = 1;
+  size_t lds = 0;
+  InstDev hI{};
+  InstDev* dI = nullptr;
+  RunDev* dR = nullptr;
+  int32_t* blk_inst = nullptr;
+  int32_t* blk_row0 = nullptr;
+  int64_t nblocks = 0;
+  double* dH = nullptr;
+  int64_t K = 0;
+  int64_t cur_step = -1;
+  bool poisoned = false;
+  bool timing = false;
+  std::vector<TimerPair> timers;
+  std::vector<hipEvent_t> spare_events;
+  asi_timing tm{};
+};
+
+namespace {
+
+#define HIPCHK(expr, sim)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      if (sim) (sim)->poisoned = true;                                                 \
+      return fail(ASI_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    }                                                                                  \
+  } while (0)
+
+hipEvent_t take_event(asi_sim* s) {
+  if (!s->spare_events.empty()) {
+    hipEvent_t e = s->spare_events.back();
+    s->spare_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch one field pass of the handle's (single) instance.
+void field_pass(asi_sim* s) {
+  TimerPair tp{};
+  if (s->timing) {
+    tp.a = take_event(s);
+    tp.b = take_event(s);
+    tp.kind = 0;
+    (void)hipEventRecord(tp.a, s->stream);
+  }
+  launch_field(s->dI, s->dR, s->blk_inst, s->blk_row0, s->nblocks, s->stream);
+  if (s->timing) {
+    (void)hipEventRecord(tp.b, s->stream);
+    s->timers.push_back(tp);
+  }
+}
+
+void relax_pass(asi_sim* s) {
+  TimerPair tp{};
+  if (s->timing) {
+    tp.a = take_event(s);
+    tp.b = take_event(s);
+    tp.kind = 1;
+    (void)hipEventRecord(tp.a, s->stream);
+  }
+  launch_relax(s->dI, s->dR, 1, s->relax_waves, s->lds, s->stream);
+  if (s->timing) {
+    (void)hipEventRecord(tp.b, s->stream);
+    s->timers.push_back(tp);
+  }
+}
+
+void harvest_timers(asi_sim* s) {
+  for (auto& tp : s->timers) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, tp.a, tp.b) == hipSuccess) {
+      if (tp.kind == 0) {
+        s->tm.field_launches++;
+        s->tm.field_ms += ms;
+      } else {
+        s->tm.relax_launches++;
+        s->tm.relax_ms += ms;
+      }
+    }
+    s->spare_events.push_back(tp.a);
+    s->spare_events.push_back(tp.b);
+  }
+  s->timers.clear();
+}
+
+asi_status check_handle(asi_sim* s) {
+  if (!s) return fail(ASI_EINVAL, "null handle");
+  if (s->poisoned) return fail(ASI_ESTATE, "handle poisoned by an earlier device error");
+  return ASI_OK;
+}
+
+asi_status sync_and_check(asi_sim* s) {
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    s->poisoned = true;
+    return fail(ASI_EDEVICE, std::string("device error: ") + hipGetErrorString(e));
+  }
+  if (s->timing) harvest_timers(s);
+  return ASI_OK;
+}
+
+asi_status validate(const asi_params* p) {
+  if (!p) return fail(ASI_EINVAL, "params is NULL");
+  if (p->struct_size != sizeof(asi_params))
+    return fail(ASI_EINVAL, "asi_params.struct_size mismatch");
+  if (p->n < 1 || p->n >= (int64_t)0x7fffffff) return fail(ASI_EINVAL, "n out of range");
+  if (!p->xy || !p->theta || !p->hk) return fail(ASI_EINVAL, "xy, theta and hk are required");
+  if (!(std::isfinite(p->alpha))) return fail(ASI_EINVAL, "alpha must be finite");
+  if (!(p->neighbor_distance >= 0.0) || !std::isfinite(p->neighbor_distance))
+    return fail(ASI_EINVAL, "neighbor_distance must be finite and >= 0");
+  if (!(p->b > 0) || !(p->c > 0) || !(p->beta > 0) || !(p->gamma > 0) || !std::isfinite(p->b) ||
+      !std::isfinite(p->c) || !std::isfinite(p->beta) || !std::isfinite(p->gamma))
+    return fail(ASI_EINVAL, "astroid parameters b, c, beta, gamma must be finite and > 0");
+  if (!(p->thermal_std >= 0.0) || !std::isfinite(p->thermal_std))
+    return fail(ASI_EINVAL, "thermal_std must be finite and >= 0");
+  if (p->max_flips_per_step < 0 || p->flip_log_capacity < 0)
+    return fail(ASI_EINVAL, "negative cap");
+  for (int64_t i = 0; i < p->n; ++i) {
+    if (!std::isfinite(p->xy[2 * i]) || !std::isfinite(p->xy[2 * i + 1]) ||
+        !std::isfinite(p->theta[i]))
+      return fail(ASI_EINVAL, "non-finite position or angle at magnet " + std::to_string(i));
+    if (!(p->hk[i] > 0.0) || !std::isfinite(p->hk[i]))
+      return fail(ASI_EINVAL, "hk must be finite and > 0 (magnet " + std::to_string(i) + ")");
+    if (p->spin0 && p->spin0[i] != 1 && p->spin0[i] != -1)
+      return fail(ASI_EINVAL, "spin0 values must be +1 or -1");
+  }
+  return ASI_OK;
+}
+
+template <class T>
+T* dalloc(asi_sim* s, size_t count) {
+  return static_cast<T*>(s->mem.alloc(sizeof(T) * count));
+}
+
+// Bytes a handle will hold on the device (used for admission control).
+size_t footprint_estimate(int64_t n, int64_t D, int64_t K, int64_t log_cap) {
+  const int64_t nsl = (n + kSlice - 1) / kSlice;
+  size_t slots = (size_t)nsl * kSlice * (size_t)D;
+  size_t b = slots * (4 + 8 + 8 + 8);
+  b += (size_t)n * (4 + 8 + 8 + 8 + 1 + 8 * 5);
+  b += (size_t)nsl * 12 + (size_t)log_cap * 8 + (size_t)K * 20;
+  b += 1 << 16;
+  return b;
+}
+
+asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
+  asi_status st = validate(p);
+  if (st != ASI_OK) return st;
+  if (const char* f = std::getenv("ASI_FAIL_ALLOC")) s->mem.fail_next = (f[0] == '1');
+  if (dev) s->mem.dev = *dev;
+  if (dev && dev->stream) {
+    s->stream = (hipStream_t)dev->stream;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking), s);
+    s->own_stream = true;
+  }
+  s->mem.st = s->stream;
+  const int64_t n = p->n;
+  s->n = n;
+
+  // host: unit vectors (libm), cell grid and the cell sort
+  std::vector<double> x(n), y(n), mx(n), my(n);
+  double xmin = p->xy[0], xmax = p->xy[0], ymin = p->xy[1], ymax = p->xy[1];
+  for (int64_t i = 0; i < n; ++i) {
+    x[i] = p->xy[2 * i];
+    y[i] = p->xy[2 * i + 1];
+    mx[i] = std::cos(p->theta[i]);
+    my[i] = std::sin(p->theta[i]);
+    xmin = std::min(xmin, x[i]);
+    xmax = std::max(xmax, x[i]);
+    ymin = std::min(ymin, y[i]);
+    ymax = std::max(ymax, y[i]);
+  }
+  const double cut = p->neighbor_distance + 1e-9;
+  const double cut2 = cut * cut;
+  double cs = std::max(cut * (1.0 + 1e-6), 1e-6);
+  const double cells_cap = 4.0 * (double)n + 1024.0;
+  while (((xmax - xmin) / cs + 1.0) * ((ymax - ymin) / cs + 1.0) > cells_cap) cs *= 2.0;
+  const int64_t gx = (int64_t)std::floor((xmax - xmin) / cs) + 1;
+  const int64_t gy = (int64_t)std::floor((ymax - ymin) / cs) + 1;
+  std::vector<int32_t> cx(n), cy(n), cstart(gx * gy + 1, 0), cmem(n);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t a = (int64_t)std::floor((x[i] - xmin) / cs);
+    int64_t b = (int64_t)std::floor((y[i] - ymin) / cs);
+    cx[i] = (int32_t)std::min(std::max(a, (int64_t)0), gx - 1);
+    cy[i] = (int32_t)std::min(std::max(b, (int64_t)0), gy - 1);
+    cstart[(int64_t)cy[i] * gx + cx[i] + 1]++;
+  }
+  for (int64_t c = 0; c < gx * gy; ++c) cstart[c + 1] += cstart[c];
+  {
+    std::vector<int32_t> fill(cstart.begin(), cstart.end() - 1);
+    for (int64_t i = 0; i < n; ++i) cmem[fill[(int64_t)cy[i] * gx + cx[i]]++] = (int32_t)i;
+  }
+
+  // device: inputs
+  double* dx = dalloc<double>(s, n);
+  double* dy = dalloc<double>(s, n);
+  double* dmx = dalloc<double>(s, n);
+  double* dmy = dalloc<double>(s, n);
+  double* dhk = dalloc<double>(s, n);
+  int8_t* ds = dalloc<int8_t>(s, n);
+  int32_t* dcx = dalloc<int32_t>(s, n);
+  int32_t* dcy = dalloc<int32_t>(s, n);
+  int32_t* dcs = dalloc<int32_t>(s, gx * gy + 1);
+  int32_t* dcm = dalloc<int32_t>(s, n);
+  int32_t* dlen = dalloc<int32_t>(s, n);
+  int32_t* ddup = dalloc<int32_t>(s, 1);
+  if (!dx || !dy || !dmx || !dmy || !dhk || !ds || !dcx || !dcy || !dcs || !dcm || !dlen || !ddup)
+    return fail(ASI_ENOMEM, "device allocation failed (inputs)");
+  std::vector<int8_t> s0(n, 1);
+  if (p->spin0) std::memcpy(s0.data(), p->spin0, n);
+  HIPCHK(hipMemcpyAsync(dx, x.data(), 8 * n, hipMemcpyHostToDevice, s->stream), s);
+  HIPCHK(hipMemcpyAsync(dy, y.data(), 8 * n, hipMemcpyHostToDevice, s->stream), s);
+  HIPCHK(hipMemcpyAsync(dmx, mx.data(), 8 * n, hipMemcpyHostToDevice, s->stream), s);
+  HIPCHK(hipMemcpyAsync(dmy, my.data(), 8 * n, hipMemcpyHostToDevice, s->stream), s);
+  HIPCHK(hipMemcpyAsync(dhk, p->hk, 8 * n, hipMemcpyHostToDevice, s->stream), s);
+  HIPCHK(hipMemcpyAsync(ds, s0.data(), n, hipMemcpyHostToDevice, s->stream), s);
+  HIPCHK(hipMemcpyAsync(dcx, cx.data(), 4 * n, hipMemcpyHostToDevice, s->stream), s);
+  HIPCHK(hipMemcpyAsync(dcy, cy.data(), 4 * n, hipMemcpyHostToDevice, s->stream), s);
+  HIPCHK(hipMemcpyAsync(dcs, cstart.data(), 4 * (gx * gy + 1), hipMemcpyHostToDevice, s->stream),
+         s);
+  HIPCHK(hipMemcpyAsync(dcm, cmem.data(), 4 * n, hipMemcpyHostToDevice, s->stream), s);
+  HIPCHK(hipMemsetAsync(ddup, 0, 4, s->stream), s);
+
+  // device: neighbour counts -> padded row length
+  launch_neighbour_count(dx, dy, dcx, dcy, dcs, dcm, n, gx, gy, cut2, dlen, ddup, s->stream);
+  std::vector<int32_t> len(n);
+  int32_t dup = 0;
+  HIPCHK(hipMemcpyAsync(len.data(), dlen, 4 * n, hipMemcpyDeviceToHost, s->stream), s);
+  HIPCHK(hipMemcpyAsync(&dup, ddup, 4, hipMemcpyDeviceToHost, s->stream), s);
+  HIPCHK(hipStreamSynchronize(s->stream), s);
+  if (dup) return fail(ASI_EINVAL, "coincident magnets (zero separation)");
+  int64_t E = 0;
+  int32_t D = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    E += len[i];
+    D = std::max(D, len[i]);
+  }
+  s->E = E;
+  s->D = D;
+  const int64_t nsl = (n + kSlice - 1) / kSlice;
+  const size_t slots = (size_t)nsl * kSlice * (size_t)std::max(D, 1);
+  int32_t* dcol = dalloc<int32_t>(s, slots);
+  double* dA = dalloc<double>(s, slots);
+  double* dB = dalloc<double>(s, slots);
+  double* dBr = dalloc<double>(s, slots);
+  if (!dcol || !dA || !dB || !dBr) return fail(ASI_ENOMEM, "device allocation failed (neighbour tables)");
+  // rows of a partial last slice stay padded
+  HIPCHK(hipMemsetAsync(dcol, 0xff, 4 * slots, s->stream), s);
+  HIPCHK(hipMemsetAsync(dA, 0, 8 * slots, s->stream), s);
+  HIPCHK(hipMemsetAsync(dB, 0, 8 * slots, s->stream), s);
+  HIPCHK(hipMemsetAsync(dBr, 0, 8 * slots, s->stream), s);
+  if (D > 0)
+    launch_neighbour_fill(dx, dy, dmx, dmy, dcx, dcy, dcs, dcm, n, gx, gy, cut2, p->alpha, D, dcol,
+                          dA, dB, dBr, s->stream);
+  HIPCHK(hipStreamSynchronize(s->stream), s);
+  s->mem.release(dcx);
+  s->mem.release(dcy);
+  s->mem.release(dcs);
+  s->mem.release(dcm);
+  s->mem.release(ddup);
+  s->mem.release(dx);
+  s->mem.release(dy);
+
+  // device: state
+  const int64_t log_cap = p->flip_log_capacity > 0 ? p->flip_log_capacity : 4 * n + 65536;
+  InstDev& I = s->hI;
+  I.n = n;
+  I.D = D;
+  s->l1s = relax_l1_shift(n);
+  I.l1_shift = s->l1s;
+  I.len = dlen;
+  I.col = dcol;
+  I.A = dA;
+  I.B = dB;
+  I.Br = dBr;
+  I.mx = dmx;
+  I.my = dmy;
+  I.hk = dhk;
+  I.b = p->b;
+  I.c = p->c;
+  I.e_par = 2.0 / p->gamma;
+  I.e_perp = 2.0 / p->beta;
+  I.sigma = p->thermal_std;
+  I.seed = p->thermal_seed;
+  I.H = nullptr;
+  I.K = 0;
+  I.s = ds;
+  I.hd_par = dalloc<double>(s, n);
+  I.hd_perp = dalloc<double>(s, n);
+  I.h_par = dalloc<double>(s, n);
+  I.h_perp = dalloc<double>(s, n);
+  I.key = dalloc<double>(s, n);
+  I.t1key = dalloc<double>(s, nsl);
+  I.t1idx = dalloc<uint32_t>(s, nsl);
+  I.log_t = dalloc<int32_t>(s, log_cap);
+  I.log_j = dalloc<int32_t>(s, log_cap);
+  I.log_cap = log_cap;
+  I.step_flips = nullptr;
+  I.max_flips = p->max_flips_per_step > 0 ? p->max_flips_per_step : 64 * n;
+  s->dI = dalloc<InstDev>(s, 1);
+  s->dR = dalloc<RunDev>(s, 1);
+  s->nblocks = (n + kFieldBlock - 1) / kFieldBlock;
+  s->blk_inst = dalloc<int32_t>(s, s->nblocks);
+  s->blk_row0 = dalloc<int32_t>(s, s->nblocks);
+  if (!I.hd_par || !I.hd_perp || !I.h_par || !I.h_perp || !I.key || !I.t1key || !I.t1idx ||
+      !I.log_t || !I.log_j || !s->dI || !s->dR || !s->blk_inst || !s->blk_row0)
+    return fail(ASI_ENOMEM, "device allocation failed (state)");
+  HIPCHK(hipMemsetAsync(I.h_par, 0, 8 * n, s->stream), s);
+  HIPCHK(hipMemsetAsync(I.h_perp, 0, 8 * n, s->stream), s);
+  std::vector<int32_t> bi(s->nblocks, 0), br(s->nblocks);
+  for (int64_t b = 0; b < s->nblocks; ++b) br[b] = (int32_t)(b * kFieldBlock);
+  HIPCHK(hipMemcpyAsync(s->blk_inst, bi.data(), 4 * s->nblocks, hipMemcpyHostToDevice, s->stream),
+         s);
+  HIPCHK(hipMemcpyAsync(s->blk_row0, br.data(), 4 * s->nblocks, hipMemcpyHostToDevice, s->stream),
+         s);
+  HIPCHK(hipMemcpyAsync(s->dI, &s->hI, sizeof(InstDev), hipMemcpyHostToDevice, s->stream), s);
+  launch_set_run(s->dR, -1, -1, 0, 1, -1, s->stream);
+  s->relax_waves = std::min(kMaxRelaxWaves, std::max(1, (D + 63) / 64));
+  if (const char* w = std::getenv("ASI_RELAX_WAVES")) {
+    int v = std::atoi(w);
+    if (v >= 1 && v <= kMaxRelaxWaves) s->relax_waves = v;
+  }
+  s->lds = relax_lds_bytes(n, s->l1s);
+  return sync_and_check(s);
+}
+
+asi_status upload_desc(asi_sim* s) {
+  HIPCHK(hipMemcpyAsync(s->dI, &s->hI, sizeof(InstDev), hipMemcpyHostToDevice, s->stream), s);
+  return ASI_OK;
+}
+
+asi_status read_run(asi_sim* s, RunDev* r) {
+  HIPCHK(hipMemcpyAsync(r, s->dR, sizeof(RunDev), hipMemcpyDeviceToHost, s->stream), s);
+  return sync_and_check(s);
+}
+
+// steps [t0, t1) of the protocol (t0 may be -1 for the zero-field step)
+asi_status run_steps(asi_sim* s, int64_t t0, int64_t t1, int64_t* flips_out) {
+  launch_set_run(s->dR, t0, t1, t0 < t1 ? 1 : 0, 0, 0, s->stream);
+  for (int64_t t = t0; t < t1; ++t) {
+    field_pass(s);
+    relax_pass(s);
+  }
+  RunDev r{};
+  asi_status st = read_run(s, &r);
+  if (st != ASI_OK) return st;
+  s->cur_step = r.cur_step;
+  if (flips_out) *flips_out = r.flips_call;
+  if (r.status == ASI_ELOOP)
+    return fail(ASI_ELOOP, "a relax exceeded max_flips_per_step at step " +
+                               std::to_string(r.cur_step));
+  return ASI_OK;
+}
+
+}  // namespace
+
+// ======================================================================== ABI
+extern "C" {
+
+const char* asi_last_error(void) { return g_err.c_str(); }
+
+asi_status asi_create(const asi_params* params, const asi_device* dev, asi_handle* out) {
+  if (!out) return fail(ASI_EINVAL, "out is NULL");
+  *out = nullptr;
+  auto* s = new (std::nothrow) asi_sim();
+  if (!s) return fail(ASI_ENOMEM, "host allocation failed");
+  asi_status st = create_impl(params, dev, s);
+  if (st != ASI_OK) {
+    std::string keep = g_err;
+    (void)hipStreamSynchronize(s->stream);
+    s->mem.release_all();
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    g_err = keep;
+    return st;
+  }
+  *out = s;
+  return ASI_OK;
+}
+
+asi_status asi_set_field_protocol(asi_handle h, int64_t n_steps, const double* h_xy) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (n_steps < 0 || n_steps >= (int64_t)0x7fffffff || (n_steps > 0 && !h_xy))
+    return fail(ASI_EINVAL, "bad protocol");
+  for (int64_t k = 0; k < 2 * n_steps; ++k)
+    if (!std::isfinite(h_xy[k])) return fail(ASI_EINVAL, "non-finite protocol value");
+  HIPCHK(hipStreamSynchronize(h->stream), h);
+  if (h->dH) h->mem.release(h->dH);
+  if (h->hI.step_flips) h->mem.release(h->hI.step_flips);
+  h->dH = dalloc<double>(h, std::max<int64_t>(1, 2 * n_steps));
+  h->hI.step_flips = dalloc<int32_t>(h, std::max<int64_t>(1, n_steps));
+  if (!h->dH || !h->hI.step_flips) return fail(ASI_ENOMEM, "device allocation failed (protocol)");
+  if (n_steps > 0)
+    HIPCHK(hipMemcpyAsync(h->dH, h_xy, 16 * n_steps, hipMemcpyHostToDevice, h->stream), h);
+  HIPCHK(hipMemsetAsync(h->hI.step_flips, 0, 4 * std::max<int64_t>(1, n_steps), h->stream), h);
+  h->K = n_steps;
+  h->hI.H = h->dH;
+  h->hI.K = n_steps;
+  if (h->cur_step >= n_steps) h->cur_step = -1;
+  st = upload_desc(h);
+  if (st != ASI_OK) return st;
+  return sync_and_check(h);
+}
+
+asi_status asi_relax(asi_handle h, int64_t* flips_out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  return run_steps(h, h->cur_step, h->cur_step + 1, flips_out);
+}
+
+asi_status asi_run(asi_handle h, int64_t t_begin, int64_t t_end, int64_t* flips_out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (t_begin < 0 || t_begin > t_end || t_end > h->K)
+    return fail(ASI_EINVAL, "step range outside the protocol");
+  if (flips_out) *flips_out = 0;
+  if (t_begin == t_end) return ASI_OK;
+  return run_steps(h, t_begin, t_end, flips_out);
+}
+
+asi_status asi_compute_fields(asi_handle h, int64_t t) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (t < -1 || t >= h->K) return fail(ASI_EINVAL, "step outside the protocol");
+  launch_set_run(h->dR, t, t + 1, 1, 0, 0, h->stream);
+  field_pass(h);
+  launch_set_run(h->dR, t, t, 0, 0, 0, h->stream);
+  return sync_and_check(h);
+}
+
+asi_status asi_get_state(asi_handle h, int8_t* spins, double* h_par, double* h_perp,
+                         int64_t* step_out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (spins) HIPCHK(hipMemcpyAsync(spins, h->hI.s, h->n, hipMemcpyDeviceToHost, h->stream), h);
+  if (h_par)
+    HIPCHK(hipMemcpyAsync(h_par, h->hI.h_par, 8 * h->n, hipMemcpyDeviceToHost, h->stream), h);
+  if (h_perp)
+    HIPCHK(hipMemcpyAsync(h_perp, h->hI.h_perp, 8 * h->n, hipMemcpyDeviceToHost, h->stream), h);
+  st = sync_and_check(h);
+  if (st != ASI_OK) return st;
+  if (step_out) *step_out = h->cur_step;
+  return ASI_OK;
+}
+
+asi_status asi_set_state(asi_handle h, const int8_t* spins, int64_t step) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (!spins) return fail(ASI_EINVAL, "spins is NULL");
+  if (step < -1 || step >= std::max<int64_t>(h->K, 0)) {
+    if (!(step == -1)) return fail(ASI_EINVAL, "step outside the protocol");
+  }
+  for (int64_t i = 0; i < h->n; ++i)
+    if (spins[i] != 1 && spins[i] != -1) return fail(ASI_EINVAL, "spins must be +1 or -1");
+  HIPCHK(hipStreamSynchronize(h->stream), h);
+  HIPCHK(hipMemcpyAsync(h->hI.s, spins, h->n, hipMemcpyHostToDevice, h->stream), h);
+  launch_set_run(h->dR, step, step, 0, 1, step, h->stream);
+  h->cur_step = step;
+  return sync_and_check(h);
+}
+
+asi_status asi_get_flip_log(asi_handle h, int64_t cap, int32_t* step, int32_t* idx,
+                            int64_t* count_out, uint64_t* hash_out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (cap < 0 || (cap > 0 && (!step || !idx))) return fail(ASI_EINVAL, "bad log buffers");
+  RunDev r{};
+  st = read_run(h, &r);
+  if (st != ASI_OK) return st;
+  const int64_t m = std::min(std::min(cap, r.flips), h->hI.log_cap);
+  if (m > 0) {
+    HIPCHK(hipMemcpyAsync(step, h->hI.log_t, 4 * m, hipMemcpyDeviceToHost, h->stream), h);
+    HIPCHK(hipMemcpyAsync(idx, h->hI.log_j, 4 * m, hipMemcpyDeviceToHost, h->stream), h);
+    st = sync_and_check(h);
+    if (st != ASI_OK) return st;
+  }
+  if (count_out) *count_out = r.flips;
+  if (hash_out) *hash_out = r.hash;
+  return ASI_OK;
+}
+
+asi_status asi_get_step_flips(asi_handle h, int32_t* out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (!out) return fail(ASI_EINVAL, "out is NULL");
+  if (h->K > 0)
+    HIPCHK(hipMemcpyAsync(out, h->hI.step_flips, 4 * h->K, hipMemcpyDeviceToHost, h->stream), h);
+  return sync_and_check(h);
+}
+
+asi_status asi_get_info(asi_handle h, asi_info* out) {
+  if (!h || !out) return fail(ASI_EINVAL, "null argument");
+  out->n = h->n;
+  out->n_edges = h->E;
+  out->max_degree = h->D;
+  out->relax_waves = h->relax_waves;
+  out->device_bytes = (int64_t)h->mem.total;
+  out->field_pass_bytes = 20.0 * (double)h->E + 53.0 * (double)h->n;
+  out->flip_log_capacity = h->hI.log_cap;
+  return ASI_OK;
+}
+
+asi_status asi_set_timing(asi_handle h, int32_t enable) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  st = sync_and_check(h);
+  if (st != ASI_OK) return st;
+  h->timing = enable != 0;
+  h->tm = asi_timing{};
+  return ASI_OK;
+}
+
+asi_status asi_get_timing(asi_handle h, asi_timing* out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (!out) return fail(ASI_EINVAL, "out is NULL");
+  st = sync_and_check(h);
+  if (st != ASI_OK) return st;
+  *out = h->tm;
+  return ASI_OK;
+}
+
+asi_status asi_destroy(asi_handle h) {
+  if (!h) return ASI_OK;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto& tp : h->timers) {
+    (void)hipEventDestroy(tp.a);
+    (void)hipEventDestroy(tp.b);
+  }
+  for (auto e : h->spare_events) (void)hipEventDestroy(e);
+  h->mem.release_all();
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  return ASI_OK;
+}
+
+}  // extern "C"
+
+// ======================================================================== batch
+namespace {
+
+// A device-resident table of instances driven by one field launch and one
+// relax launch per step.  Used by asi_batch_run and by the server.
+struct Table {
+  DevMem mem;
+  int32_t count = 0;
+  InstDev* dI = nullptr;
+  RunDev* dR = nullptr;
+  int32_t* blk_inst = nullptr;
+  int32_t* blk_row0 = nullptr;
+  int64_t nblocks = 0;
+  int32_t waves = 1;
+  size_t lds = 0;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~Table() {
+    drop_graph();
+    mem.release_all();
+  }
+};
+
+// (Re)build the launch tables for the given instance descriptors.
+asi_status table_build(Table& T, const std::vector<InstDev>& insts,
+                       const std::vector<int32_t>& waves, const std::vector<size_t>& lds,
+                       hipStream_t st) {
+  T.drop_graph();
+  T.mem.st = st;
+  T.mem.release_all();
+  T.count = (int32_t)insts.size();
+  std::vector<int32_t> bi, br;
+  T.waves = 1;
+  T.lds = 0;
+  for (int32_t k = 0; k < T.count; ++k) {
+    const int64_t nb = (insts[k].n + kFieldBlock - 1) / kFieldBlock;
+    for (int64_t b = 0; b < nb; ++b) {
+      bi.push_back(k);
+      br.push_back((int32_t)(b * kFieldBlock));
+    }
+    T.waves = std::max(T.waves, waves[k]);
+    T.lds = std::max(T.lds, lds[k]);
+  }
+  if (const char* w = std::getenv("ASI_BATCH_RELAX_WAVES")) {
+    int v = std::atoi(w);
+    if (v >= 1 && v <= kMaxRelaxWaves) T.waves = v;
+  }
+  T.nblocks = (int64_t)bi.size();
+  T.dI = static_cast<InstDev*>(T.mem.alloc(sizeof(InstDev) * std::max(1, T.count)));
+  T.dR = static_cast<RunDev*>(T.mem.alloc(sizeof(RunDev) * std::max(1, T.count)));
+  T.blk_inst = static_cast<int32_t*>(T.mem.alloc(4 * std::max<int64_t>(1, T.nblocks)));
+  T.blk_row0 = static_cast<int32_t*>(T.mem.alloc(4 * std::max<int64_t>(1, T.nblocks)));
+  if (!T.dI || !T.dR || !T.blk_inst || !T.blk_row0)
+    return fail(ASI_ENOMEM, "device allocation failed (batch tables)");
+  if (T.count > 0) {
+    HIPCHK(hipMemcpyAsync(T.dI, insts.data(), sizeof(InstDev) * T.count, hipMemcpyHostToDevice, st),
+           (asi_sim*)nullptr);
+  }
+  if (T.nblocks > 0) {
+    HIPCHK(hipMemcpyAsync(T.blk_inst, bi.data(), 4 * T.nblocks, hipMemcpyHostToDevice, st),
+           (asi_sim*)nullptr);
+    HIPCHK(hipMemcpyAsync(T.blk_row0, br.data(), 4 * T.nblocks, hipMemcpyHostToDevice, st),
+           (asi_sim*)nullptr);
+  }
+  HIPCHK(hipStreamSynchronize(st), (asi_sim*)nullptr);
+  return ASI_OK;
+}
+
+void table_step(Table& T, hipStream_t st) {
+  launch_field(T.dI, T.dR, T.blk_inst, T.blk_row0, T.nblocks, st);
+  launch_relax(T.dI, T.dR, T.count, T.waves, T.lds, st);
+}
+
+asi_status table_capture(Table& T, hipStream_t st) {
+  T.drop_graph();
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), (asi_sim*)nullptr);
+  table_step(T, st);
+  HIPCHK(hipStreamEndCapture(st, &T.graph), (asi_sim*)nullptr);
+  HIPCHK(hipGraphInstantiate(&T.exec, T.graph, nullptr, nullptr, 0), (asi_sim*)nullptr);
+  return ASI_OK;
+}
+
+}  // namespace
+
+extern "C" asi_status asi_batch_run(asi_handle* hs, int32_t count, int32_t use_graph,
+                                    int64_t* flips_out) {
+  if (!hs || count < 1) return fail(ASI_EINVAL, "no handles");
+  for (int32_t k = 0; k < count; ++k) {
+    asi_status st = check_handle(hs[k]);
+    if (st != ASI_OK) return st;
+    for (int32_t m = 0; m < k; ++m)
+      if (hs[m] == hs[k]) return fail(ASI_EINVAL, "a handle appears twice in the batch");
+  }
+  std::vector<InstDev> insts(count);
+  std::vector<RunDev> runs(count);
+  std::vector<int32_t> waves(count);
+  std::vector<size_t> lds(count);
+  int64_t max_steps = 0;
+  for (int32_t k = 0; k < count; ++k) {
+    asi_sim* h = hs[k];
+    asi_status st = read_run(h, &runs[k]);
+    if (st != ASI_OK) return st;
+    insts[k] = h->hI;
+    waves[k] = h->relax_waves;
+    lds[k] = h->lds;
+    RunDev& r = runs[k];
+    r.t = h->cur_step + 1;
+    r.t_end = h->K;
+    r.active = r.t < r.t_end ? 1 : 0;
+    r.status = 0;
+    r.flips_call = 0;
+    max_steps = std::max(max_steps, r.t_end - r.t);
+  }
+  hipStream_t st = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), (asi_sim*)nullptr);
+  asi_status res = ASI_OK;
+  {
+    Table T;
+    T.mem.dev = hs[0]->mem.dev;
+    res = table_build(T, insts, waves, lds, st);
+    if (res == ASI_OK) {
+      hipError_t e = hipMemcpyAsync(T.dR, runs.data(), sizeof(RunDev) * count,
+                                    hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) res = fail(ASI_EDEVICE, hipGetErrorString(e));
+    }
+    if (res == ASI_OK && use_graph && max_steps > 0) res = table_capture(T, st);
+    if (res == ASI_OK) {
+      for (int64_t s = 0; s < max_steps; ++s) {
+        if (T.exec) {
+          hipError_t e = hipGraphLaunch(T.exec, st);
+          if (e != hipSuccess) {
+            res = fail(ASI_EDEVICE, hipGetErrorString(e));
+            break;
+          }
+        } else {
+          table_step(T, st);
+        }
+      }
+    }
+    if (res == ASI_OK) {
+      hipError_t e = hipMemcpyAsync(runs.data(), T.dR, sizeof(RunDev) * count,
+                                    hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e == hipSuccess) e = hipGetLastError();
+      if (e != hipSuccess) res = fail(ASI_EDEVICE, hipGetErrorString(e));
+    }
+    (void)hipStreamSynchronize(st);
+  }
+  (void)hipStreamDestroy(st);
+  if (res != ASI_OK) {
+    if (res == ASI_EDEVICE)
+      for (int32_t k = 0; k < count; ++k) hs[k]->poisoned = true;
+    return res;
+  }
+  bool loop = false;
+  for (int32_t k = 0; k < count; ++k) {
+    asi_sim* h = hs[k];
+    HIPCHK(hipMemcpyAsync(h->dR, &runs[k], sizeof(RunDev), hipMemcpyHostToDevice, h->stream), h);
+    HIPCHK(hipStreamSynchronize(h->stream), h);
+    h->cur_step = runs[k].cur_step;
+    if (flips_out) flips_out[k] = runs[k].flips_call;
+    if (runs[k].status == ASI_ELOOP) loop = true;
+  }
+  if (loop) return fail(ASI_ELOOP, "an instance exceeded max_flips_per_step");
+  return ASI_OK;
+}
+
+// ======================================================================== server
+namespace {
+
+struct Job {
+  int64_t id = 0;
+  asi_params p{};
+  std::vector<double> xy, theta, hk, H;
+  std::vector<int8_t> spin0;
+  int64_t K = 0;
+  size_t foot = 0;
+  asi_sim* h = nullptr;  // while resident
+  int32_t slot = -1;
+  int state = 0;         // 0 queued, 1 resident, 2 done, 3 failed
+  asi_status err = ASI_OK;
+  std::vector<int8_t> spins_out;
+  int64_t flips = 0;
+  uint64_t hash = 0;
+  double t_admit = 0, t_done = 0;
+};
+
+// Upper bound of any magnet's neighbour count from cell occupancies (cells
+// of side >= cutoff): the population of its 3 x 3 cell block.
+int64_t degree_bound(const asi_params* p) {
+  const int64_t n = p->n;
+  double xmin = p->xy[0], xmax = p->xy[0], ymin = p->xy[1], ymax = p->xy[1];
+  for (int64_t i = 0; i < n; ++i) {
+    xmin = std::min(xmin, p->xy[2 * i]);
+    xmax = std::max(xmax, p->xy[2 * i]);
+    ymin = std::min(ymin, p->xy[2 * i + 1]);
+    ymax = std::max(ymax, p->xy[2 * i + 1]);
+  }
+  double cs = std::max((p->neighbor_distance + 1e-9) * (1.0 + 1e-6), 1e-6);
+  const double cap = 4.0 * (double)n + 1024.0;
+  while (((xmax - xmin) / cs + 1.0) * ((ymax - ymin) / cs + 1.0) > cap) cs *= 2.0;
+  const int64_t gx = (int64_t)std::floor((xmax - xmin) / cs) + 1;
+  const int64_t gy = (int64_t)std::floor((ymax - ymin) / cs) + 1;
+  std::vector<int32_t> cnt(gx * gy, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t a = std::min(std::max((int64_t)std::floor((p->xy[2 * i] - xmin) / cs), (int64_t)0), gx - 1);
+    int64_t b = std::min(std::max((int64_t)std::floor((p->xy[2 * i + 1] - ymin) / cs), (int64_t)0), gy - 1);
+    cnt[b * gx + a]++;
+  }
+  int64_t best = 0;
+  for (int64_t y = 0; y < gy; ++y)
+    for (int64_t x = 0; x < gx; ++x) {
+      if (!cnt[y * gx + x]) continue;
+      int64_t s = 0;
+      for (int64_t yy = std::max<int64_t>(0, y - 1); yy <= std::min(gy - 1, y + 1); ++yy)
+        for (int64_t xx = std::max<int64_t>(0, x - 1); xx <= std::min(gx - 1, x + 1); ++xx)
+          s += cnt[yy * gx + xx];
+      best = std::max(best, s - 1);
+    }
+  return std::min<int64_t>(best, n - 1);
+}
+
+}  // namespace
+
+struct asi_server {
+  asi_device dev{};
+  hipStream_t stream = nullptr;
+  size_t budget = 0, used = 0;
+  int32_t max_slots = 0;
+  int64_t next_id = 0;
+  std::map<int64_t, std::unique_ptr<Job>> jobs;
+  std::deque<int64_t> queue;
+  std::vector<int64_t> slots;  // job id per slot, -1 free
+  Table T;
+  bool dirty = true;
+  std::vector<RunDev> runs;
+};
+
+namespace {
+
+asi_status server_rebuild(asi_server* S) {
+  std::vector<InstDev> insts(S->max_slots);
+  std::vector<int32_t> waves(S->max_slots, 1);
+  std::vector<size_t> lds(S->max_slots, 0);
+  for (int32_t k = 0; k < S->max_slots; ++k) {
+    if (S->slots[k] < 0) {
+      insts[k] = InstDev{};
+      insts[k].n = 0;
+      continue;
+    }
+    Job& J = *S->jobs[S->slots[k]];
+    insts[k] = J.h->hI;
+    waves[k] = J.h->relax_waves;
+    lds[k] = J.h->lds;
+  }
+  asi_status st = table_build(S->T, insts, waves, lds, S->stream);
+  if (st != ASI_OK) return st;
+  HIPCHK(hipMemcpyAsync(S->T.dR, S->runs.data(), sizeof(RunDev) * S->max_slots,
+                        hipMemcpyHostToDevice, S->stream),
+         (asi_sim*)nullptr);
+  S->dirty = false;
+  return ASI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+asi_status asi_server_create(const asi_device* dev, size_t hbm_budget_bytes, int32_t max_slots,
+                             asi_server_t* out) {
+  if (!out || max_slots < 1 || hbm_budget_bytes == 0) return fail(ASI_EINVAL, "bad server args");
+  auto* S = new (std::nothrow) asi_server();
+  if (!S) return fail(ASI_ENOMEM, "host allocation failed");
+  if (dev) S->dev = *dev;
+  S->dev.stream = nullptr;
+  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete S;
+    return fail(ASI_EDEVICE, "stream creation failed");
+  }
+  S->dev.stream = S->stream;
+  S->budget = hbm_budget_bytes;
+  S->max_slots = max_slots;
+  S->slots.assign(max_slots, -1);
+  S->runs.assign(max_slots, RunDev{});
+  S->T.mem.dev = S->dev;
+  *out = S;
+  return ASI_OK;
+}
+
+asi_status asi_server_submit(asi_server_t S, const asi_params* p, int64_t n_steps,
+                             const double* h_xy, int64_t* job_id_out) {
+  if (!S || !job_id_out) return fail(ASI_EINVAL, "null argument");
+  asi_status st = validate(p);
+  if (st != ASI_OK) return st;
+  if (n_steps < 1 || !h_xy) return fail(ASI_EINVAL, "a job needs a protocol of >= 1 step");
+  auto J = std::make_unique<Job>();
+  J->p = *p;
+  J->xy.assign(p->xy, p->xy + 2 * p->n);
+  J->theta.assign(p->theta, p->theta + p->n);
+  J->hk.assign(p->hk, p->hk + p->n);
+  if (p->spin0) J->spin0.assign(p->spin0, p->spin0 + p->n);
+  J->H.assign(h_xy, h_xy + 2 * n_steps);
+  J->K = n_steps;
+  const int64_t log_cap = p->flip_log_capacity > 0 ? p->flip_log_capacity : 4 * p->n + 65536;
+  J->foot = footprint_estimate(p->n, degree_bound(p), n_steps, log_cap);
+  if (J->foot > S->budget) return fail(ASI_ENOMEM, "job footprint exceeds the server budget");
+  J->id = S->next_id++;
+  *job_id_out = J->id;
+  S->queue.push_back(J->id);
+  S->jobs[J->id] = std::move(J);
+  return ASI_OK;
+}
+
+asi_status asi_server_step(asi_server_t S, int32_t* active_out) {
+  if (!S) return fail(ASI_EINVAL, "null server");
+  // admit in arrival order while a slot and the budget allow
+  while (!S->queue.empty()) {
+    int32_t slot = -1;
+    for (int32_t k = 0; k < S->max_slots; ++k)
+      if (S->slots[k] < 0) {
+        slot = k;
+        break;
+      }
+    if (slot < 0) break;
+    Job& J = *S->jobs[S->queue.front()];
+    if (S->used + J.foot > S->budget) break;
+    S->queue.pop_front();
+    asi_params p = J.p;
+    p.xy = J.xy.data();
+    p.theta = J.theta.data();
+    p.hk = J.hk.data();
+    p.spin0 = J.spin0.empty() ? nullptr : J.spin0.data();
+    asi_handle h = nullptr;
+    asi_status st = asi_create(&p, &S->dev, &h);
+    if (st == ASI_OK) st = asi_set_field_protocol(h, J.K, J.H.data());
+    if (st != ASI_OK) {
+      if (h) asi_destroy(h);
+      J.state = 3;
+      J.err = st;
+      J.t_done = now_s();
+      continue;
+    }
+    J.h = h;
+    J.slot = slot;
+    J.state = 1;
+    J.t_admit = now_s();
+    S->used += J.foot;
+    S->slots[slot] = J.id;
+    RunDev r{};
+    r.t = 0;
+    r.t_end = J.K;
+    r.active = 1;
+    r.hash = 0xcbf29ce484222325ull;
+    r.cur_step = -1;
+    S->runs[slot] = r;
+    S->dirty = true;
+  }
+  int32_t resident = 0;
+  for (int32_t k = 0; k < S->max_slots; ++k) resident += S->slots[k] >= 0;
+  if (resident > 0) {
+    if (S->dirty) {
+      asi_status st = server_rebuild(S);
+      if (st != ASI_OK) return st;
+    }
+    table_step(S->T, S->stream);
+    HIPCHK(hipMemcpyAsync(S->runs.data(), S->T.dR, sizeof(RunDev) * S->max_slots,
+                          hipMemcpyDeviceToHost, S->stream),
+           (asi_sim*)nullptr);
+    HIPCHK(hipStreamSynchronize(S->stream), (asi_sim*)nullptr);
+    HIPCHK(hipGetLastError(), (asi_sim*)nullptr);
+    // retire finished jobs
+    for (int32_t k = 0; k < S->max_slots; ++k) {
+      if (S->slots[k] < 0) continue;
+      RunDev& r = S->runs[k];
+      if (r.active) continue;
+      Job& J = *S->jobs[S->slots[k]];
+      J.flips = r.flips;
+      J.hash = r.hash;
+      J.spins_out.resize(J.p.n);
+      HIPCHK(hipMemcpyAsync(J.spins_out.data(), J.h->hI.s, J.p.n, hipMemcpyDeviceToHost, S->stream),
+             (asi_sim*)nullptr);
+      HIPCHK(hipStreamSynchronize(S->stream), (asi_sim*)nullptr);
+      J.state = r.status == 0 ? 2 : 3;
+      J.err = r.status == 0 ? ASI_OK : ASI_ELOOP;
+      J.t_done = now_s();
+      asi_destroy(J.h);
+      J.h = nullptr;
+      S->used -= J.foot;
+      S->slots[k] = -1;
+      S->runs[k] = RunDev{};
+      S->dirty = true;
+    }
+  }
+  if (active_out) {
+    int32_t a = (int32_t)S->queue.size();
+    for (int32_t k = 0; k < S->max_slots; ++k) a += S->slots[k] >= 0;
+    *active_out = a;
+  }
+  return ASI_OK;
+}
+
+asi_status asi_server_poll(asi_server_t S, int64_t job_id, int32_t* done_out) {
+  if (!S || !done_out) return fail(ASI_EINVAL, "null argument");
+  auto it = S->jobs.find(job_id);
+  if (it == S->jobs.end()) return fail(ASI_EINVAL, "unknown job");
+  *done_out = it->second->state >= 2 ? 1 : 0;
+  return ASI_OK;
+}
+
+asi_status asi_server_take(asi_server_t S, int64_t job_id, int8_t* spins, int64_t* flips,
+                           uint64_t* flip_hash, double* t_admit, double* t_done) {
+  if (!S) return fail(ASI_EINVAL, "null server");
+  auto it = S->jobs.find(job_id);
+  if (it == S->jobs.end()) return fail(ASI_EINVAL, "unknown job");
+  Job& J = *it->second;
+  if (J.state < 2) return fail(ASI_EBUSY, "job not finished");
+  asi_status err = J.err;
+  if (spins && !J.spins_out.empty()) std::memcpy(spins, J.spins_out.data(), J.p.n);
+  if (flips) *flips = J.flips;
+  if (flip_hash) *flip_hash = J.hash;
+  if (t_admit) *t_admit = J.t_admit;
+  if (t_done) *t_done = J.t_done;
+  S->jobs.erase(it);
+  if (err != ASI_OK) return fail(err, "job failed");
+  return ASI_OK;
+}
+
+asi_status asi_server_destroy(asi_server_t S) {
+  if (!S) return ASI_OK;
+  (void)hipStreamSynchronize(S->stream);
+  for (auto& kv : S->jobs)
+    if (kv.second->h) asi_destroy(kv.second->h);
+  S->jobs.clear();
+  S->T.drop_graph();
+  S->T.mem.release_all();
+  (void)hipStreamDestroy(S->stream);
+  delete S;
+  return ASI_OK;
+}
+
+}  // extern "C"

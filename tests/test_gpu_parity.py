@@ -1,0 +1,288 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Bar: flip sequences (step, magnet) and final spins bit-exact; fields within
+1e-12 of the per-magnet summand scale S_i = alpha*sum_j |g_ij| + |H| + |h_th|
+(cancellation makes |h_i| itself a poor denominator).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import native as N
+from paper_2002_11401_amd import asi
+from paper_2002_11401_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+FIELD_TOL = 1e-12
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+def oracle_run(w, t0=0, t1=None, spins=None):
+    o = N.Oracle.from_workload(w)
+    o.set_spins(w.spin0 if spins is None else spins)
+    r = o.run(w.H, t0, t1)
+    return o, r
+
+
+def gpu_sim(w, **kw):
+    return asi.Sim.from_workload(w, **kw)
+
+
+def assert_fields_close(o, sim, H, t):
+    s, hp, hq, _ = sim.state()
+    o.set_spins(s)
+    ep, eq, scale = o.fields(H, t)
+    bad_p = np.abs(hp - ep) > FIELD_TOL * scale
+    bad_q = np.abs(hq - eq) > FIELD_TOL * scale
+    assert not bad_p.any() and not bad_q.any(), (
+        f"fields off at {np.nonzero(bad_p | bad_q)[0][:5]}; "
+        f"max rel {np.max(np.abs(hp - ep) / scale):.3e} / {np.max(np.abs(hq - eq) / scale):.3e}")
+    return float(max(np.max(np.abs(hp - ep) / scale), np.max(np.abs(hq - eq) / scale)))
+
+
+def assert_same_flips(log, r, spins_gpu, spins_oracle):
+    n = min(len(log["idx"]), len(r["idx"]))
+    st_g, ix_g = log["step"], log["idx"]
+    if log["count"] != r["n_flips"] or not (np.array_equal(st_g, r["step"]) and
+                                            np.array_equal(ix_g, r["idx"])):
+        diff = np.nonzero((st_g[:n] != r["step"][:n]) | (ix_g[:n] != r["idx"][:n]))[0]
+        k = int(diff[0]) if len(diff) else n
+        raise AssertionError(
+            f"flip sequences differ at flip {k}: gpu {log['count']} flips, oracle "
+            f"{r['n_flips']}; gpu {list(zip(st_g[k:k+3], ix_g[k:k+3]))} oracle "
+            f"{list(zip(r['step'][k:k+3], r['idx'][k:k+3]))}; oracle gaps {r['gaps']}")
+    assert np.array_equal(spins_gpu, spins_oracle)
+    assert log["hash"] == asi.flip_hash(r["step"], r["idx"])
+
+
+# ------------------------------------------------------------------ small configs
+def test_square10_triangle_full_run_bit_exact():
+    w = W.square_10x10_triangle()
+    say("square10_triangle full run", w.n, w.n_steps)
+    sim = gpu_sim(w)
+    flips = sim.run()
+    o, r = oracle_run(w)
+    log = sim.flip_log()
+    assert flips == r["n_flips"] == log["count"]
+    assert_same_flips(log, r, sim.state()[0], o.spins())
+    assert np.array_equal(sim.step_flips(), r["per_step"])
+    assert_fields_close(o, sim, w.H[-1], w.n_steps - 1)
+    info = sim.info()
+    assert info["n_edges"] == o.num_edges == 1596
+
+
+@pytest.mark.parametrize("seed", list(range(8)))
+def test_random_instances_bit_exact(seed):
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(30, 700))
+    xy, theta = W.random_cloud(n, 600 + seed, min_sep=0.4)
+    hk = W.disorder_hk(n, 0.1, 0.1, seed)
+    H = W.rotating(30, 0.12, 25) if seed % 2 else W.linear_ramp(30, 0.15, -0.15, 17.0 * seed)
+    w = W.Workload(f"cloud{seed}", xy, theta, rng.choice([-1, 1], n).astype(np.int8), hk, H,
+                   alpha=float(rng.uniform(0.002, 0.03)),
+                   neighbor_distance=float(rng.uniform(0.5, 6.0)),
+                   b=float(rng.uniform(0.3, 1.0)), c=1.0, beta=float(rng.uniform(1.5, 4.0)),
+                   gamma=float(rng.uniform(2.0, 4.0)),
+                   thermal_std=float(rng.choice([0.0, 0.004, 0.02])), thermal_seed=seed + 7)
+    say("random cloud", seed, n, w.neighbor_distance, w.thermal_std)
+    sim = gpu_sim(w)
+    sim.run()
+    o, r = oracle_run(w)
+    assert_same_flips(sim.flip_log(), r, sim.state()[0], o.spins())
+    assert_fields_close(o, sim, w.H[-1], w.n_steps - 1)
+
+
+def test_fields_of_every_step_match_oracle():
+    """One full-field pass per step (no relax) on a kagome patch with
+    thermal noise, for random spin states."""
+    xy, theta = W.kagome(12)
+    n = len(theta)
+    rng = np.random.default_rng(3)
+    w = W.Workload("kagome12", xy, theta, np.ones(n, np.int8), W.disorder_hk(n, 0.15, 0.05, 3),
+                   W.rotating(8, 0.08, 8), alpha=0.002, neighbor_distance=3.0, b=1, c=1,
+                   beta=3, gamma=3, thermal_std=0.005, thermal_seed=2)
+    say("kagome12 field passes", n)
+    sim = gpu_sim(w)
+    o = N.Oracle.from_workload(w)
+    worst = 0.0
+    for t in range(-1, w.n_steps):
+        spins = rng.choice([-1, 1], n).astype(np.int8)
+        sim.set_state(spins, -1)
+        sim.compute_fields(t)
+        worst = max(worst, assert_fields_close(o, sim, w.H[t] if t >= 0 else np.zeros(2), t))
+    say("worst relative field error", worst)
+
+
+# ------------------------------------------------------------------ paper-scale configs
+def test_pinwheel100_reversal_bit_exact():
+    w = W.pinwheel_100x100_reversal()
+    say("pinwheel100 reversal full run", w.n, w.n_steps)
+    sim = gpu_sim(w)
+    assert sim.info()["n_edges"] == 11701684
+    sim.run()
+    o, r = oracle_run(w)
+    say("pinwheel100 flips", r["n_flips"], "gaps", r["gaps"])
+    assert_same_flips(sim.flip_log(), r, sim.state()[0], o.spins())
+    assert np.array_equal(sim.step_flips(), r["per_step"])
+    assert_fields_close(o, sim, w.H[-1], w.n_steps - 1)
+
+
+def test_kagome1m_sampled_windows_bit_exact():
+    """~1M-magnet kagome with thermal noise: the whole 2000-step run on the
+    GPU; the oracle re-runs sampled windows of steps from the GPU's own
+    state at the window start, and must produce the same flips."""
+    w = W.kagome_1m_rotating()
+    say("kagome577 full run", w.n, w.n_steps)
+    sim = gpu_sim(w)
+    assert sim.info()["n_edges"] == 31870074
+    o = N.Oracle.from_workload(w)
+    windows = [(0, 6), (437, 441), (1500, 1503)]
+    t = 0
+    for (a, b) in windows:
+        if a > t:
+            sim.run(t, a)
+        s0, _, _, _ = sim.state()
+        before = sim.flip_log(cap=0)["count"]
+        sim.run(a, b)
+        say("kagome window", a, b)
+        o.set_spins(s0)
+        r = o.run(w.H, a, b)
+        log = sim.flip_log()
+        lg = dict(step=log["step"][before:], idx=log["idx"][before:],
+                  count=log["count"] - before, hash=None)
+        assert lg["count"] == r["n_flips"]
+        assert np.array_equal(lg["step"], r["step"]) and np.array_equal(lg["idx"], r["idx"])
+        assert np.array_equal(sim.state()[0], o.spins())
+        assert_fields_close(o, sim, w.H[b - 1], b - 1)
+        t = b
+    sim.run(t, w.n_steps)
+    assert sim.state()[3] == w.n_steps - 1
+
+
+# ------------------------------------------------------------------ invariances
+def test_checkpoint_resume_bitwise():
+    w = W.square_10x10_triangle()
+    say("checkpoint/resume")
+    a = gpu_sim(w)
+    a.run(0, 120)
+    s_mid, _, _, step = a.state()
+    assert step == 119
+    log_a = a.flip_log()
+    a.run(120, w.n_steps)
+    full = a.flip_log()
+    b = gpu_sim(w)
+    b.set_state(s_mid, step)
+    b.run(120, w.n_steps)
+    lb = b.flip_log()
+    k = log_a["count"]
+    assert np.array_equal(lb["idx"], full["idx"][k:])
+    assert np.array_equal(lb["step"], full["step"][k:])
+    assert np.array_equal(a.state()[0], b.state()[0])
+
+
+def test_relax_is_idempotent_and_zero_field_step():
+    w = W.square_10x10_triangle()
+    say("relax idempotent")
+    sim = gpu_sim(w)
+    assert sim.relax() == 0          # all +1 under zero field and alpha=1e-3: stable
+    sim.run(0, 50)
+    assert sim.relax() == 0          # already relaxed at step 49
+
+
+def test_batched_equals_plain_bitwise():
+    ws = W.batched_sweep(count=12, seed=4, n_steps=60, side_range=(6, 30))
+    say("batched vs plain", [w.n for w in ws])
+    plain = []
+    for w in ws:
+        s = gpu_sim(w)
+        s.run()
+        plain.append((s.flip_log(), s.state()))
+    for use_graph in (False, True):
+        sims = [gpu_sim(w) for w in ws]
+        flips = asi.batch_run(sims, use_graph=use_graph)
+        for k, s in enumerate(sims):
+            lg = s.flip_log()
+            assert flips[k] == lg["count"] == plain[k][0]["count"]
+            assert lg["hash"] == plain[k][0]["hash"]
+            assert np.array_equal(lg["idx"], plain[k][0]["idx"])
+            st = s.state()
+            assert np.array_equal(st[0], plain[k][1][0])
+            assert np.array_equal(st[1], plain[k][1][1])   # fields bitwise
+            assert np.array_equal(st[2], plain[k][1][2])
+
+
+def test_served_equals_plain_bitwise():
+    jobs = W.served_stream(count=10, seed=5, n_range=(200, 4000), steps_range=(20, 60))
+    say("served vs plain", [(j.family, j.n_target, j.d) for j in jobs])
+    srv = asi.Server(hbm_budget_bytes=2 << 30, max_slots=4)
+    ids = []
+    pending = list(jobs)
+    active = 1
+    while pending or active:
+        if pending:
+            ids.append((pending[0], srv.submit(pending[0].workload())))
+            pending.pop(0)
+        active = srv.step()
+    for job, jid in ids:
+        assert srv.poll(jid)
+        res = srv.take(jid)
+        w = job.workload()
+        s = gpu_sim(w)
+        s.run()
+        lg = s.flip_log()
+        assert res["flips"] == lg["count"] and res["hash"] == lg["hash"]
+        assert np.array_equal(res["spins"], s.state()[0])
+    srv.close()
+
+
+# ------------------------------------------------------------------ edge cases
+def test_single_magnet_and_no_neighbours():
+    say("single magnet")
+    w = W.Workload("one", np.array([[0.0, 0.0]]), np.array([0.0]), np.ones(1, np.int8),
+                   np.array([0.2]), np.array([[-0.21, 0.0], [-0.19, 0.0]]), alpha=0.01,
+                   neighbor_distance=0.0, b=1, c=1, beta=3, gamma=3)
+    sim = gpu_sim(w)
+    assert sim.info()["n_edges"] == 0
+    assert sim.run() == 1
+    assert sim.state()[0][0] == -1
+    # d = 0 on a lattice: independent magnets
+    xy, theta = W.square_closed(4)
+    w2 = W.Workload("sq4_d0", xy, theta, np.ones(len(theta), np.int8),
+                    W.disorder_hk(len(theta), 0.2, 0.05, 1), W.linear_ramp(40, 0.3, -0.3, 45),
+                    alpha=0.001, neighbor_distance=0.0, b=1, c=1, beta=3, gamma=3)
+    s2 = gpu_sim(w2)
+    s2.run()
+    o, r = oracle_run(w2)
+    assert_same_flips(s2.flip_log(), r, s2.state()[0], o.spins())
+
+
+def test_errors_and_flip_cap():
+    say("errors")
+    w = W.square_10x10_triangle()
+    sim = gpu_sim(w, max_flips_per_step=3)
+    with pytest.raises(asi.AsiError) as e:
+        sim.run()
+    assert e.value.status == asi.ASI_ELOOP
+    with pytest.raises(asi.AsiError) as e:
+        sim.run(0, w.n_steps + 1)
+    assert e.value.status == asi.ASI_EINVAL
+    with pytest.raises(asi.AsiError) as e:
+        asi.Sim(np.zeros((2, 2)), [0.0, 1.0], [0.2, 0.2], alpha=0.001, neighbor_distance=1.0,
+                b=1, c=1, beta=3, gamma=3)
+    assert e.value.status == asi.ASI_EINVAL   # coincident magnets
+
+
+def test_small_log_capacity_keeps_counting():
+    w = W.square_10x10_triangle()
+    say("log capacity")
+    sim = gpu_sim(w, flip_log_capacity=10)
+    sim.run()
+    lg = sim.flip_log()
+    o, r = oracle_run(w)
+    assert lg["count"] == r["n_flips"] and len(lg["idx"]) == 10
+    assert np.array_equal(lg["idx"], r["idx"][:10])
+    assert lg["hash"] == asi.flip_hash(r["step"], r["idx"])
