@@ -50,32 +50,13 @@ def cpu_baseline(w, target_s: float = 15.0):
                 flips_per_s=flips / dt)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="kagome577_rotating")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); independent instances "
-              "would shard across GPUs with no communication, which this build does not run.",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    from paper_2002_11401_amd import asi, workloads
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
+def bench_plain(args, asi, workloads, torch):
     w = workloads.NAMED[args.workload]()
     K = w.n_steps if args.steps is None else min(args.steps, w.n_steps)
-    sim = asi.Sim.from_workload(w)
+    # every step re-gathers every row: the measured full-field pass
+    sim = asi.Sim.from_workload(w, full_field_pass=True)
     info = sim.info()
     E, N = info["n_edges"], info["n"]
-
     # warmup: the first steps, then back to the start state
     W = min(args.warmup, w.n_steps)
     if W > 0:
@@ -106,12 +87,14 @@ def main():
         "config": {"workload": w.name, "magnets": N, "neighbour_pairs": E,
                    "max_degree": info["max_degree"], "neighbor_distance": w.neighbor_distance,
                    "thermal_std": w.thermal_std, "protocol_steps": w.n_steps,
-                   "parallelism": "single instance, one GPU"},
+                   "field_pass": "full every step", "parallelism": "single instance, one GPU"},
         "flips_per_s": flips / dt,
         "flips": flips,
         "field_calcs_per_s": N * K / dt,
         "field_pass": {"avg_us": field_avg_s * 1e6, "launches": tm["field_launches"],
-                       "algorithmic_bytes": info["field_pass_bytes"]},
+                       "algorithmic_bytes": info["field_pass_bytes"],
+                       "neighbour_interactions_per_s": E / field_avg_s,
+                       "field_calcs_per_s": N / field_avg_s},
         "relax": {"ms_total": tm["relax_ms"], "launches": tm["relax_launches"],
                   "ns_per_flip": tm["relax_ms"] * 1e6 / max(1, flips),
                   "flips_per_s_in_kernel": flips / max(1e-9, tm["relax_ms"] / 1e3)},
@@ -124,7 +107,133 @@ def main():
     sim.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def bench_batched(args, asi, workloads, torch):
+    """Uneven sweep of instances: one batched run (one field launch and one
+    relax launch per step, replayed from a captured graph) against the same
+    instances run one after another with asi_run."""
+    K = 500 if args.steps is None else args.steps
+    ws = workloads.batched_sweep(count=args.count, seed=4, n_steps=K)
+    sims = [asi.Sim.from_workload(w) for w in ws]
+    ntot = sum(w.n for w in ws)
+    etot = sum(s.info()["n_edges"] for s in sims)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = []
+    for s in sims:
+        s.run()
+        plain.append(s.flip_log(cap=0))
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    plain_spins = [s.state()[0] for s in sims]
+    for s, w in zip(sims, ws):
+        s.set_state(w.spin0, -1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flips = asi.batch_run(sims, use_graph=True)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    same = all(s.flip_log(cap=0)["hash"] == p["hash"] and np.array_equal(s.state()[0], sp)
+               for s, p, sp in zip(sims, plain, plain_spins))
+    for s in sims:
+        s.close()
+    return {"metric": METRIC, "value": len(ws) / t_bat, "unit": "runs/s", "n_gpus": 1,
+            "steps": K, "warmup": 0, "ms_per_step": t_bat / K * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"batched sweep of {len(ws)} square/pinwheel instances",
+                       "magnets_total": ntot, "neighbour_pairs_total": etot,
+                       "parallelism": "one launch per phase over all instances"},
+            "batched_runs_per_s": len(ws) / t_bat, "plain_runs_per_s": len(ws) / t_seq,
+            "speedup_vs_plain": t_seq / t_bat, "plain_seconds": t_seq, "batched_seconds": t_bat,
+            "flips": int(flips.sum()), "bitwise_identical_to_plain": bool(same)}
+
+
+def bench_served(args, asi, workloads, torch):
+    """Poisson stream of jobs into the continuous-batching server; latency =
+    completion - arrival.  Every job is then re-run alone for comparison."""
+    jobs = workloads.served_stream(count=args.jobs, seed=5, rate_per_s=args.rate,
+                                   n_range=(1e3, args.max_n))
+    srv = asi.Server(hbm_budget_bytes=int(args.budget_gb * (1 << 30)), max_slots=args.slots)
+    wl = {}
+    ids = {}
+    lat = {}
+    t0 = time.perf_counter()
+    pending = list(jobs)
+    active = 0
+    while pending or active:
+        now = time.perf_counter() - t0
+        while pending and pending[0].arrival_s <= now:
+            j = pending.pop(0)
+            wl[j.job] = j.workload()
+            ids[j.job] = srv.submit(wl[j.job])
+        active = srv.step()
+        for job, jid in list(ids.items()):
+            if job not in lat and srv.poll(jid):
+                lat[job] = time.perf_counter() - t0
+        if not active and pending:
+            time.sleep(max(0.0, pending[0].arrival_s - (time.perf_counter() - t0)))
+    t_all = time.perf_counter() - t0
+    res = {job: srv.take(jid) for job, jid in ids.items()}
+    srv.close()
+    lats = np.array([lat[j.job] - j.arrival_s for j in jobs])
+    # the same jobs, one after another, each alone
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    same = True
+    for j in jobs:
+        s = asi.Sim.from_workload(wl[j.job], device="hip")
+        s.run()
+        lg = s.flip_log(cap=0)
+        same &= lg["hash"] == res[j.job]["hash"] and np.array_equal(s.state()[0], res[j.job]["spins"])
+        s.close()
+    t_plain = time.perf_counter() - t1
+    return {"metric": METRIC, "value": len(jobs) / t_all, "unit": "runs/s", "n_gpus": 1,
+            "steps": int(sum(j.n_steps for j in jobs)), "warmup": 0,
+            "ms_per_step": t_all / max(1, sum(j.n_steps for j in jobs)) * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"Poisson stream of {len(jobs)} jobs at {args.rate}/s, "
+                                   f"1e3..{args.max_n:g} magnets, square/pinwheel/kagome",
+                       "slots": args.slots, "hbm_budget_gb": args.budget_gb,
+                       "parallelism": "continuous batching, one GPU"},
+            "served_runs_per_s": len(jobs) / t_all, "plain_runs_per_s": len(jobs) / t_plain,
+            "speedup_vs_plain": t_plain / t_all,
+            "latency_s": {"p50": float(np.percentile(lats, 50)),
+                          "p99": float(np.percentile(lats, 99)), "max": float(lats.max())},
+            "bitwise_identical_to_plain": bool(same)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--mode", choices=["plain", "batched", "served"], default="plain")
+    ap.add_argument("--workload", default="kagome577_rotating")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--count", type=int, default=256, help="batched: instances")
+    ap.add_argument("--jobs", type=int, default=2000, help="served: jobs")
+    ap.add_argument("--rate", type=float, default=50.0, help="served: arrivals per second")
+    ap.add_argument("--max-n", type=float, default=1e6, help="served: largest job")
+    ap.add_argument("--slots", type=int, default=64, help="served: resident jobs")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="served: HBM budget")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); independent instances "
+              "would shard across GPUs with no communication, which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2002_11401_amd import asi, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    fn = {"plain": bench_plain, "batched": bench_batched, "served": bench_served}[args.mode]
+    print(json.dumps(fn(args, asi, workloads, torch)), flush=True)
 
 
 if __name__ == "__main__":

@@ -79,6 +79,10 @@ typedef struct {
   int64_t max_flips_per_step;/* 0 => 64 * n; a relax exceeding it => ASI_ELOOP  */
   int64_t flip_log_capacity; /* entries kept in the flip log; 0 => 4n + 65536.
                                 Flips beyond it are counted and hashed only.    */
+  int32_t full_field_pass;   /* 1: every step re-gathers the dipolar sum of every
+                                magnet; 0 (default): only of magnets with a
+                                neighbour flipped since their last gather.  The
+                                results are bitwise identical either way.       */
 } asi_params;
 
 /* Build an instance: copies the inputs, builds the neighbour lists and the

@@ -47,7 +47,7 @@ class AsiParams(C.Structure):
                 ("b", C.c_double), ("c", C.c_double), ("beta", C.c_double),
                 ("gamma", C.c_double), ("thermal_std", C.c_double),
                 ("thermal_seed", C.c_uint64), ("max_flips_per_step", C.c_int64),
-                ("flip_log_capacity", C.c_int64)]
+                ("flip_log_capacity", C.c_int64), ("full_field_pass", C.c_int32)]
 
 
 class AsiInfo(C.Structure):
@@ -180,7 +180,8 @@ def _close_all():
 
 
 def _params(xy, theta, hk, spin0, alpha, neighbor_distance, b, c, beta, gamma,
-            thermal_std=0.0, thermal_seed=0, max_flips_per_step=0, flip_log_capacity=0):
+            thermal_std=0.0, thermal_seed=0, max_flips_per_step=0, flip_log_capacity=0,
+            full_field_pass=False):
     keep = [np.ascontiguousarray(xy, dtype=np.float64).reshape(-1),
             np.ascontiguousarray(theta, dtype=np.float64),
             np.ascontiguousarray(hk, dtype=np.float64),
@@ -191,7 +192,8 @@ def _params(xy, theta, hk, spin0, alpha, neighbor_distance, b, c, beta, gamma,
     p = AsiParams(C.sizeof(AsiParams), n, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[3]),
                   _ptr(keep[2]), float(alpha), float(neighbor_distance), float(b), float(c),
                   float(beta), float(gamma), float(thermal_std), int(thermal_seed),
-                  int(max_flips_per_step), int(flip_log_capacity))
+                  int(max_flips_per_step), int(flip_log_capacity),
+                  1 if full_field_pass else 0)
     return p, keep
 
 
@@ -200,11 +202,12 @@ class Sim:
 
     def __init__(self, xy, theta, hk, spin0=None, *, alpha, neighbor_distance, b, c, beta,
                  gamma, thermal_std=0.0, thermal_seed=0, H=None, max_flips_per_step=0,
-                 flip_log_capacity=0, device="torch"):
+                 flip_log_capacity=0, full_field_pass=False, device="torch"):
         L = library()
         self._dev = device if not isinstance(device, str) else make_device(device)
         p, keep = _params(xy, theta, hk, spin0, alpha, neighbor_distance, b, c, beta, gamma,
-                          thermal_std, thermal_seed, max_flips_per_step, flip_log_capacity)
+                          thermal_std, thermal_seed, max_flips_per_step, flip_log_capacity,
+                          full_field_pass)
         h = C.c_void_p()
         _check(L.asi_create(C.byref(p), C.byref(self._dev.struct), C.byref(h)))
         self._h = h

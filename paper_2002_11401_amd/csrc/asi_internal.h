@@ -41,9 +41,11 @@ struct InstDev {
   uint64_t seed;          // thermal Philox key
   const double* H;        // [K][2] applied field per step
   int64_t K;
+  int32_t full_pass;      // 1: gather every row every step; 0: only dirty rows
   // mutable state
   int8_t* s;              // [n] spins
-  double* hd_par;         // [n] dipolar field at step start, canonical order
+  uint8_t* dirty;         // [n] row's dipolar sum is stale (a neighbour flipped)
+  double* hd_par;         // [n] dipolar field of the last gather, canonical order
   double* hd_perp;
   double* h_par;          // [n] total field (dipolar + applied + thermal)
   double* h_perp;

@@ -101,15 +101,43 @@ __device__ inline void coupling(double fx, double fy, double fmx, double fmy, do
   B = alpha * (3.0 * (pf * as) * inv5 - pm * inv3);
 }
 
+// Cross-lane moves of a double within rows of 16 lanes by DPP.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+__device__ inline double readlane_f64(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// Maximum over the 64 lanes, returned to every lane: butterfly within each
+// row of 16 (quad swaps, half-row and row mirrors), then the four row
+// results through scalar reads.
+__device__ inline double wave_max_f64(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_f64<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_f64<0x141>(v));  // row_half_mirror
+  v = fmax(v, dpp_f64<0x140>(v));  // row_mirror
+  const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
+  const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
+  return fmax(fmax(r0, r1), fmax(r2, r3));
+}
+
 // Wave-wide argmax of (key, payload) where lane order is index order:
-// largest key, and among equal keys the lowest lane.  All 64 lanes call.
+// largest key, and among equal keys the lowest lane.  All 64 lanes call;
+// the result is uniform.
 __device__ inline void wave_argmax(double& key, uint32_t& payload) {
-  double m = key;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  const double m = wave_max_f64(key);
   const unsigned long long bal = __ballot(key == m);
   const int src = __ffsll((unsigned long long)bal) - 1;
-  payload = __shfl(payload, src, 64);
+  payload = (uint32_t)__builtin_amdgcn_readlane((int)payload, src);
   key = m;
 }
 
@@ -245,39 +273,51 @@ __global__ __launch_bounds__(kFieldBlock) void k_field(const InstDev* __restrict
   double key = 0.0;
   uint32_t payload = 0;
   if (i < n) {
-    const int32_t L = I->len[i];
-    const int64_t base = slot_of(i, D, 0);
-    const int32_t* __restrict__ col = I->col + base;
-    const double* __restrict__ A = I->A + base;
-    const double* __restrict__ B = I->B + base;
     double p = 0.0, pq = 0.0;
-    int32_t k = 0;
-    for (; k + 4 <= L; k += 4) {
-      const int32_t j0 = col[(k + 0) * kSlice], j1 = col[(k + 1) * kSlice];
-      const int32_t j2 = col[(k + 2) * kSlice], j3 = col[(k + 3) * kSlice];
-      const double a0 = A[(k + 0) * kSlice], a1 = A[(k + 1) * kSlice];
-      const double a2 = A[(k + 2) * kSlice], a3 = A[(k + 3) * kSlice];
-      const double b0 = B[(k + 0) * kSlice], b1 = B[(k + 1) * kSlice];
-      const double b2 = B[(k + 2) * kSlice], b3 = B[(k + 3) * kSlice];
-      const int s0 = s[j0], s1 = s[j1], s2 = s[j2], s3 = s[j3];
-      p += (s0 > 0) ? a0 : -a0;
-      pq += (s0 > 0) ? b0 : -b0;
-      p += (s1 > 0) ? a1 : -a1;
-      pq += (s1 > 0) ? b1 : -b1;
-      p += (s2 > 0) ? a2 : -a2;
-      pq += (s2 > 0) ? b2 : -b2;
-      p += (s3 > 0) ? a3 : -a3;
-      pq += (s3 > 0) ? b3 : -b3;
+    const bool gather = I->full_pass || I->dirty[i];
+    if (gather) {
+      const int32_t L = I->len[i];
+      const int64_t base = slot_of(i, D, 0);
+      const int32_t* __restrict__ col = I->col + base;
+      const double* __restrict__ A = I->A + base;
+      const double* __restrict__ B = I->B + base;
+      // Chunks of 8 neighbours; the columns of the next chunk are fetched
+      // with the couplings and spins of the current one, so each chunk costs
+      // one round trip.  Accumulation stays in ascending neighbour order.
+      int32_t jc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) jc[u] = (u < L) ? col[u * kSlice] : 0;
+      for (int32_t k = 0; k < L; k += 8) {
+        double a[8], b[8];
+        int sg[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const bool ok = k + u < L;
+          a[u] = ok ? A[(k + u) * kSlice] : 0.0;
+          b[u] = ok ? B[(k + u) * kSlice] : 0.0;
+          sg[u] = ok ? s[jc[u]] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) jc[u] = (k + 8 + u < L) ? col[(k + 8 + u) * kSlice] : 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (k + u < L) {
+            p += (sg[u] > 0) ? a[u] : -a[u];
+            pq += (sg[u] > 0) ? b[u] : -b[u];
+          }
+        }
+      }
+      if (!I->full_pass) {
+        I->hd_par[i] = p;
+        I->hd_perp[i] = pq;
+        I->dirty[i] = 0;
+      }
+    } else {
+      // no neighbour flipped since the last gather: the canonical sum is
+      // unchanged bit for bit
+      p = I->hd_par[i];
+      pq = I->hd_perp[i];
     }
-    for (; k < L; ++k) {
-      const int32_t j = col[k * kSlice];
-      const double a = A[k * kSlice], b = B[k * kSlice];
-      const int sj = s[j];
-      p += (sj > 0) ? a : -a;
-      pq += (sj > 0) ? b : -b;
-    }
-    I->hd_par[i] = p;
-    I->hd_perp[i] = pq;
     const double mxi = I->mx[i], myi = I->my[i];
     double hp = p, hq = pq;
     if (t >= 0) {
@@ -378,6 +418,7 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
   double* __restrict__ hpp = I->h_par;
   double* __restrict__ hqp = I->h_perp;
   double* __restrict__ keyp = I->key;
+  uint8_t* __restrict__ dirtyp = I->dirty;
   const double pb = I->b, pc = I->c, ep = I->e_par, eq = I->e_perp;
   const int64_t max_flips = I->max_flips;
   const int64_t t = R->t;
@@ -481,6 +522,7 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
         hpp[i] = hp;
         hqp[i] = hq;
         keyp[i] = kk;
+        dirtyp[i] = 1;
         const int e = (int)(i >> l1s);
         if (atomicExch(&L.l1flag[e], 1) == 0) L.l1list[atomicAdd(&sh_n1, 1)] = e;
       }

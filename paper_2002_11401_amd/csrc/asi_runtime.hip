@@ -217,6 +217,8 @@ asi_status validate(const asi_params* p) {
     return fail(ASI_EINVAL, "thermal_std must be finite and >= 0");
   if (p->max_flips_per_step < 0 || p->flip_log_capacity < 0)
     return fail(ASI_EINVAL, "negative cap");
+  if (p->full_field_pass != 0 && p->full_field_pass != 1)
+    return fail(ASI_EINVAL, "full_field_pass must be 0 or 1");
   for (int64_t i = 0; i < p->n; ++i) {
     if (!std::isfinite(p->xy[2 * i]) || !std::isfinite(p->xy[2 * i + 1]) ||
         !std::isfinite(p->theta[i]))
@@ -239,7 +241,7 @@ size_t footprint_estimate(int64_t n, int64_t D, int64_t K, int64_t log_cap) {
   const int64_t nsl = (n + kSlice - 1) / kSlice;
   size_t slots = (size_t)nsl * kSlice * (size_t)D;
   size_t b = slots * (4 + 8 + 8 + 8);
-  b += (size_t)n * (4 + 8 + 8 + 8 + 1 + 8 * 5);
+  b += (size_t)n * (4 + 8 + 8 + 8 + 1 + 1 + 8 * 7);
   b += (size_t)nsl * 12 + (size_t)log_cap * 8 + (size_t)K * 20;
   b += 1 << 16;
   return b;
@@ -388,6 +390,8 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   I.H = nullptr;
   I.K = 0;
   I.s = ds;
+  I.full_pass = p->full_field_pass ? 1 : 0;
+  I.dirty = dalloc<uint8_t>(s, n);
   I.hd_par = dalloc<double>(s, n);
   I.hd_perp = dalloc<double>(s, n);
   I.h_par = dalloc<double>(s, n);
@@ -405,10 +409,11 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   s->nblocks = (n + kFieldBlock - 1) / kFieldBlock;
   s->blk_inst = dalloc<int32_t>(s, s->nblocks);
   s->blk_row0 = dalloc<int32_t>(s, s->nblocks);
-  if (!I.hd_par || !I.hd_perp || !I.h_par || !I.h_perp || !I.key || !I.t1key || !I.t1idx ||
+  if (!I.dirty || !I.hd_par || !I.hd_perp || !I.h_par || !I.h_perp || !I.key || !I.t1key || !I.t1idx ||
       !I.log_t || !I.log_j || !s->dI || !s->dR || !s->blk_inst || !s->blk_row0)
     return fail(ASI_ENOMEM, "device allocation failed (state)");
   HIPCHK(hipMemsetAsync(I.h_par, 0, 8 * n, s->stream), s);
+  HIPCHK(hipMemsetAsync(I.dirty, 1, n, s->stream), s);
   HIPCHK(hipMemsetAsync(I.h_perp, 0, 8 * n, s->stream), s);
   std::vector<int32_t> bi(s->nblocks, 0), br(s->nblocks);
   for (int64_t b = 0; b < s->nblocks; ++b) br[b] = (int32_t)(b * kFieldBlock);
@@ -418,7 +423,9 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
          s);
   HIPCHK(hipMemcpyAsync(s->dI, &s->hI, sizeof(InstDev), hipMemcpyHostToDevice, s->stream), s);
   launch_set_run(s->dR, -1, -1, 0, 1, -1, s->stream);
-  s->relax_waves = std::min(kMaxRelaxWaves, std::max(1, (D + 63) / 64));
+  // at least 4 wavefronts so the tiles touched by a flip are rescanned in
+  // parallel; one neighbour per lane where the degree allows
+  s->relax_waves = std::min(kMaxRelaxWaves, std::max(4, (D + 63) / 64));
   if (const char* w = std::getenv("ASI_RELAX_WAVES")) {
     int v = std::atoi(w);
     if (v >= 1 && v <= kMaxRelaxWaves) s->relax_waves = v;
@@ -558,6 +565,7 @@ asi_status asi_set_state(asi_handle h, const int8_t* spins, int64_t step) {
     if (spins[i] != 1 && spins[i] != -1) return fail(ASI_EINVAL, "spins must be +1 or -1");
   HIPCHK(hipStreamSynchronize(h->stream), h);
   HIPCHK(hipMemcpyAsync(h->hI.s, spins, h->n, hipMemcpyHostToDevice, h->stream), h);
+  HIPCHK(hipMemsetAsync(h->hI.dirty, 1, h->n, h->stream), h);
   launch_set_run(h->dR, step, step, 0, 1, step, h->stream);
   h->cur_step = step;
   return sync_and_check(h);

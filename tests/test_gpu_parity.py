@@ -286,3 +286,28 @@ def test_small_log_capacity_keeps_counting():
     assert lg["count"] == r["n_flips"] and len(lg["idx"]) == 10
     assert np.array_equal(lg["idx"], r["idx"][:10])
     assert lg["hash"] == asi.flip_hash(r["step"], r["idx"])
+
+
+def test_full_pass_and_dirty_row_modes_bitwise():
+    """Re-gathering only rows with a flipped neighbour gives the same bits as
+    a full-field pass every step (fields, flips, spins), and both match the
+    oracle."""
+    xy, theta = W.kagome(30)
+    n = len(theta)
+    H = W.rotating(120, 0.08, 60)
+    w = W.Workload("kagome30", xy, theta, W.polarised_spins(theta, H[0]),
+                   W.disorder_hk(n, 0.15, 0.05, 8), H, alpha=0.002, neighbor_distance=3.0,
+                   b=1, c=1, beta=3, gamma=3, thermal_std=0.005, thermal_seed=4)
+    say("full vs dirty-row field pass", n)
+    a = gpu_sim(w, full_field_pass=True)
+    b = gpu_sim(w)
+    for t0, t1 in [(0, 40), (40, 41), (41, 120)]:
+        a.run(t0, t1)
+        b.run(t0, t1)
+        sa, sb = a.state(), b.state()
+        for x, y in zip(sa[:3], sb[:3]):
+            assert np.array_equal(x, y)
+    la, lb = a.flip_log(), b.flip_log()
+    assert la["hash"] == lb["hash"] and la["count"] == lb["count"] > 0
+    o, r = oracle_run(w)
+    assert_same_flips(lb, r, b.state()[0], o.spins())
