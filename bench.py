@@ -25,6 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def progress(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 METRIC = "neighbour interactions/s & flips/s; batched/served runs/s + p99 vs plain"
 
 
@@ -54,7 +58,7 @@ def bench_plain(args, asi, workloads, torch):
     w = workloads.NAMED[args.workload]()
     K = w.n_steps if args.steps is None else min(args.steps, w.n_steps)
     # every step re-gathers every row: the measured full-field pass
-    sim = asi.Sim.from_workload(w, full_field_pass=True)
+    sim = asi.Sim.from_workload(w, field_mode="full")
     info = sim.info()
     E, N = info["n_edges"], info["n"]
     # warmup: the first steps, then back to the start state
@@ -122,9 +126,11 @@ def bench_batched(args, asi, workloads, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain = []
-    for s in sims:
+    for k, s in enumerate(sims):
         s.run()
         plain.append(s.flip_log(cap=0))
+        if k % 32 == 31:
+            progress(f"plain {k + 1}/{len(sims)} {time.perf_counter() - t0:.1f}s")
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     plain_spins = [s.state()[0] for s in sims]
@@ -132,7 +138,7 @@ def bench_batched(args, asi, workloads, torch):
         s.set_state(w.spin0, -1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    flips = asi.batch_run(sims, use_graph=True)
+    flips = asi.batch_run(sims, mode=args.batch_mode)
     torch.cuda.synchronize()
     t_bat = time.perf_counter() - t0
     same = all(s.flip_log(cap=0)["hash"] == p["hash"] and np.array_equal(s.state()[0], sp)
@@ -143,6 +149,7 @@ def bench_batched(args, asi, workloads, torch):
             "steps": K, "warmup": 0, "ms_per_step": t_bat / K * 1e3, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"batched sweep of {len(ws)} square/pinwheel instances",
+                       "batch_mode": args.batch_mode,
                        "magnets_total": ntot, "neighbour_pairs_total": etot,
                        "parallelism": "one launch per phase over all instances"},
             "batched_runs_per_s": len(ws) / t_bat, "plain_runs_per_s": len(ws) / t_seq,
@@ -162,13 +169,18 @@ def bench_served(args, asi, workloads, torch):
     t0 = time.perf_counter()
     pending = list(jobs)
     active = 0
+    last = t0
     while pending or active:
+        if time.perf_counter() - last > 10:
+            last = time.perf_counter()
+            progress(f"served: {len(lat)}/{len(jobs)} done, {active} active, "
+                     f"{last - t0:.1f}s")
         now = time.perf_counter() - t0
         while pending and pending[0].arrival_s <= now:
             j = pending.pop(0)
             wl[j.job] = j.workload()
             ids[j.job] = srv.submit(wl[j.job])
-        active = srv.step()
+        active = srv.step(args.burst_ms)
         for job, jid in list(ids.items()):
             if job not in lat and srv.poll(jid):
                 lat[job] = time.perf_counter() - t0
@@ -182,7 +194,9 @@ def bench_served(args, asi, workloads, torch):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     same = True
-    for j in jobs:
+    for k, j in enumerate(jobs):
+        if k % 20 == 19:
+            progress(f"plain re-run {k + 1}/{len(jobs)} {time.perf_counter() - t1:.1f}s")
         s = asi.Sim.from_workload(wl[j.job], device="hip")
         s.run()
         lg = s.flip_log(cap=0)
@@ -215,11 +229,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--count", type=int, default=256, help="batched: instances")
-    ap.add_argument("--jobs", type=int, default=2000, help="served: jobs")
+    ap.add_argument("--batch-mode", default="fused", choices=["lockstep", "graph", "fused"])
+    ap.add_argument("--jobs", type=int, default=300, help="served: jobs")
     ap.add_argument("--rate", type=float, default=50.0, help="served: arrivals per second")
     ap.add_argument("--max-n", type=float, default=1e6, help="served: largest job")
     ap.add_argument("--slots", type=int, default=64, help="served: resident jobs")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="served: HBM budget")
+    ap.add_argument("--burst-ms", type=float, default=20.0, help="served: device time per step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); independent instances "

@@ -79,10 +79,16 @@ typedef struct {
   int64_t max_flips_per_step;/* 0 => 64 * n; a relax exceeding it => ASI_ELOOP  */
   int64_t flip_log_capacity; /* entries kept in the flip log; 0 => 4n + 65536.
                                 Flips beyond it are counted and hashed only.    */
-  int32_t full_field_pass;   /* 1: every step re-gathers the dipolar sum of every
-                                magnet; 0 (default): only of magnets with a
-                                neighbour flipped since their last gather.  The
-                                results are bitwise identical either way.       */
+  int32_t field_mode;        /* how a magnet's dipolar sum (Eq. 3) is obtained at
+                                each field step:
+                                0 (default) carry: gathered once, then updated
+                                  by every neighbour flip across steps;
+                                1 dirty: re-gathered in ascending neighbour
+                                  order when a neighbour flipped since;
+                                2 full: re-gathered for every magnet every step.
+                                1 and 2 give bitwise identical results and
+                                fields that are a function of the spins only;
+                                0 differs from them by rounding.               */
 } asi_params;
 
 /* Build an instance: copies the inputs, builds the neighbour lists and the
@@ -111,9 +117,11 @@ asi_status asi_get_state(asi_handle h, int8_t* spins, double* h_par, double* h_p
                          int64_t* step_out);
 
 /* Overwrite the spins [n] (+-1) and the current step (-1 .. n_steps-1),
- * e.g. to resume from a checkpoint taken at a step boundary.  Fields are
- * recomputed from the spins on the next relax, so a resumed run is bitwise
- * identical to an uninterrupted one.  Resets the flip log and its hash. */
+ * e.g. to resume from a checkpoint taken at a step boundary.  Every dipolar
+ * sum is re-gathered from the spins at the next field step, so with
+ * field_mode 1 or 2 a resumed run is bitwise identical to an uninterrupted
+ * one; with field_mode 0 the carried sums it replaces differ from the
+ * re-gathered ones by rounding only.  Resets the flip log and its hash. */
 asi_status asi_set_state(asi_handle h, const int8_t* spins, int64_t step);
 
 /* Flip log: the first min(count, cap, flip_log_capacity) flips as
@@ -161,13 +169,18 @@ asi_status asi_destroy(asi_handle h);
  * on this thread. */
 const char* asi_last_error(void);
 
-/* ---- batching: many independent instances in one launch per phase -------
+/* ---- batching: many independent instances in few launches -------------
  * Runs every handle from its current step to the end of its own protocol.
- * All handles must live on the same device; the first handle's stream is
- * used.  Each instance's flips, spins and fields are bitwise identical to
+ * All handles must live on the same device; the work runs on a stream of
+ * its own.  Each instance's flips, spins and fields are bitwise identical to
  * running it alone with asi_run.  flips_out: [count] or NULL.
- * use_graph != 0 replays one captured HIP graph per field step. */
-asi_status asi_batch_run(asi_handle* hs, int32_t count, int32_t use_graph, int64_t* flips_out);
+ *   mode 0: per field step, one field launch over all instances and one
+ *           relax launch (a workgroup per instance);
+ *   mode 1: the same pair captured once in a HIP graph, replayed per step;
+ *   mode 2: one field launch, then one persistent launch in which each
+ *           instance's workgroup runs all of its remaining steps (field phase
+ *           and relax) without waiting for the other instances. */
+asi_status asi_batch_run(asi_handle* hs, int32_t count, int32_t mode, int64_t* flips_out);
 
 /* ---- serving: continuous batching of arriving simulation jobs -----------
  * A server keeps up to max_slots jobs resident on the device within
@@ -182,10 +195,11 @@ asi_status asi_server_create(const asi_device* dev, size_t hbm_budget_bytes,
  * budget. */
 asi_status asi_server_submit(asi_server_t s, const asi_params* p, int64_t n_steps,
                              const double* h_xy, int64_t* job_id_out);
-/* Advance the server: admit what fits, run one field step of every resident
- * job, retire finished ones.  active_out (may be NULL): jobs still queued or
- * resident. */
-asi_status asi_server_step(asi_server_t s, int32_t* active_out);
+/* Advance the server: admit what fits (neighbour tables built at
+ * admission), run every resident job for up to about budget_ms of device time
+ * (each job's workgroup advancing through its own protocol), retire finished
+ * ones.  active_out (may be NULL): jobs still queued or resident. */
+asi_status asi_server_step(asi_server_t s, double budget_ms, int32_t* active_out);
 /* done_out = 1 when the job has finished (non-blocking). */
 asi_status asi_server_poll(asi_server_t s, int64_t job_id, int32_t* done_out);
 /* Result of a finished job: spins [n] (may be NULL), flip count and hash,

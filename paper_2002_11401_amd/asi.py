@@ -22,6 +22,11 @@ LIB_PATH = os.path.join(HERE, "libasi.so")
 ASI_OK, ASI_EINVAL, ASI_ENOMEM, ASI_EDEVICE, ASI_ESTATE, ASI_ELOOP, ASI_EBUSY = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "ASI_OK", -1: "ASI_EINVAL", -2: "ASI_ENOMEM", -3: "ASI_EDEVICE",
                 -4: "ASI_ESTATE", -5: "ASI_ELOOP", -6: "ASI_EBUSY"}
+# asi_params.field_mode: carry the dipolar sums across steps by the flip
+# deltas, re-gather rows whose neighbours flipped, or re-gather every row
+FIELD_MODES = {"carry": 0, "dirty": 1, "full": 2}
+# asi_batch_run modes
+BATCH_MODES = {"lockstep": 0, "graph": 1, "fused": 2}
 FNV_OFFSET = 0xcbf29ce484222325
 FNV_PRIME = 0x100000001b3
 
@@ -47,7 +52,7 @@ class AsiParams(C.Structure):
                 ("b", C.c_double), ("c", C.c_double), ("beta", C.c_double),
                 ("gamma", C.c_double), ("thermal_std", C.c_double),
                 ("thermal_seed", C.c_uint64), ("max_flips_per_step", C.c_int64),
-                ("flip_log_capacity", C.c_int64), ("full_field_pass", C.c_int32)]
+                ("flip_log_capacity", C.c_int64), ("field_mode", C.c_int32)]
 
 
 class AsiInfo(C.Structure):
@@ -82,7 +87,7 @@ SIGNATURES = {
     "asi_batch_run": [P, C.c_int32, C.c_int32, P],
     "asi_server_create": [C.POINTER(AsiDevice), C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)],
     "asi_server_submit": [P, C.POINTER(AsiParams), C.c_int64, P, I64P],
-    "asi_server_step": [P, C.POINTER(C.c_int32)],
+    "asi_server_step": [P, C.c_double, C.POINTER(C.c_int32)],
     "asi_server_poll": [P, C.c_int64, C.POINTER(C.c_int32)],
     "asi_server_take": [P, C.c_int64, P, I64P, C.POINTER(C.c_uint64),
                         C.POINTER(C.c_double), C.POINTER(C.c_double)],
@@ -181,7 +186,7 @@ def _close_all():
 
 def _params(xy, theta, hk, spin0, alpha, neighbor_distance, b, c, beta, gamma,
             thermal_std=0.0, thermal_seed=0, max_flips_per_step=0, flip_log_capacity=0,
-            full_field_pass=False):
+            field_mode="carry"):
     keep = [np.ascontiguousarray(xy, dtype=np.float64).reshape(-1),
             np.ascontiguousarray(theta, dtype=np.float64),
             np.ascontiguousarray(hk, dtype=np.float64),
@@ -193,7 +198,7 @@ def _params(xy, theta, hk, spin0, alpha, neighbor_distance, b, c, beta, gamma,
                   _ptr(keep[2]), float(alpha), float(neighbor_distance), float(b), float(c),
                   float(beta), float(gamma), float(thermal_std), int(thermal_seed),
                   int(max_flips_per_step), int(flip_log_capacity),
-                  1 if full_field_pass else 0)
+                  FIELD_MODES[field_mode] if isinstance(field_mode, str) else int(field_mode))
     return p, keep
 
 
@@ -202,12 +207,12 @@ class Sim:
 
     def __init__(self, xy, theta, hk, spin0=None, *, alpha, neighbor_distance, b, c, beta,
                  gamma, thermal_std=0.0, thermal_seed=0, H=None, max_flips_per_step=0,
-                 flip_log_capacity=0, full_field_pass=False, device="torch"):
+                 flip_log_capacity=0, field_mode="carry", device="torch"):
         L = library()
         self._dev = device if not isinstance(device, str) else make_device(device)
         p, keep = _params(xy, theta, hk, spin0, alpha, neighbor_distance, b, c, beta, gamma,
                           thermal_std, thermal_seed, max_flips_per_step, flip_log_capacity,
-                          full_field_pass)
+                          field_mode)
         h = C.c_void_p()
         _check(L.asi_create(C.byref(p), C.byref(self._dev.struct), C.byref(h)))
         self._h = h
@@ -306,11 +311,12 @@ class Sim:
                     relax_launches=t.relax_launches, relax_ms=t.relax_ms)
 
 
-def batch_run(sims: Sequence[Sim], use_graph: bool = True):
-    """Run every instance to the end of its own protocol in batched launches."""
+def batch_run(sims: Sequence[Sim], mode: str = "fused"):
+    """Run every instance to the end of its own protocol in batched launches
+    (mode: 'lockstep', 'graph' or 'fused', see asi_batch_run)."""
     arr = (C.c_void_p * len(sims))(*[s.handle.value for s in sims])
     flips = np.zeros(len(sims), dtype=np.int64)
-    _check(library().asi_batch_run(arr, len(sims), 1 if use_graph else 0, _ptr(flips)))
+    _check(library().asi_batch_run(arr, len(sims), BATCH_MODES[mode], _ptr(flips)))
     return flips
 
 
@@ -344,9 +350,9 @@ class Server:
         self._n[jid.value] = len(keep[1])
         return jid.value
 
-    def step(self) -> int:
+    def step(self, budget_ms: float = 20.0) -> int:
         a = C.c_int32(0)
-        _check(library().asi_server_step(self._h, C.byref(a)))
+        _check(library().asi_server_step(self._h, float(budget_ms), C.byref(a)))
         return a.value
 
     def poll(self, jid: int) -> bool:

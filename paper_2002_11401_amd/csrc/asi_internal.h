@@ -9,15 +9,22 @@ namespace asi {
 
 // Rows per neighbour-table slice: one row per lane of a wavefront.
 constexpr int kSlice = 64;
-// Rows per block of the full-field pass (4 wavefronts).
+// Rows per block of the grid-wide field pass (4 wavefronts).
 constexpr int kFieldBlock = 256;
-// Most first-level tiles the relax kernel keeps in LDS.  A tile covers
-// 2^l1_shift consecutive magnets (at least 64).
+// Most first-level tiles the relax keeps in LDS.  A tile covers 2^l1_shift
+// consecutive magnets (at least 64).
 constexpr int kMaxL1Tiles = 2048;
 // First-level tiles per second-level group (one per lane).
 constexpr int kL2Group = 64;
 // Largest relax workgroup.
 constexpr int kMaxRelaxWaves = 16;
+
+// How the dipolar sum of a row is obtained at the start of a field step.
+enum FieldMode : int32_t {
+  kFieldCarry = 0,  // gathered once, then carried across steps by the flip deltas
+  kFieldDirty = 1,  // re-gathered (canonical order) when a neighbour flipped
+  kFieldFull = 2,   // re-gathered (canonical order) for every row every step
+};
 
 // Per-instance tables and state; device pointers.  One entry per instance
 // in a device array, so a single launch can serve many instances.
@@ -41,11 +48,12 @@ struct InstDev {
   uint64_t seed;          // thermal Philox key
   const double* H;        // [K][2] applied field per step
   int64_t K;
-  int32_t full_pass;      // 1: gather every row every step; 0: only dirty rows
+  int32_t field_mode;     // FieldMode
+  int32_t pad0;
   // mutable state
   int8_t* s;              // [n] spins
-  uint8_t* dirty;         // [n] row's dipolar sum is stale (a neighbour flipped)
-  double* hd_par;         // [n] dipolar field of the last gather, canonical order
+  uint8_t* dirty;         // [n] row's dipolar sum must be gathered at the next step
+  double* hd_par;         // [n] dipolar field (gathered, plus flip deltas)
   double* hd_perp;
   double* h_par;          // [n] total field (dipolar + applied + thermal)
   double* h_perp;
@@ -59,8 +67,8 @@ struct InstDev {
   int64_t max_flips;      // per relax
 };
 
-// Per-instance run cursor, device-resident so captured graphs can replay the
-// same launches step after step.
+// Per-instance run cursor, device-resident so repeated launches (and
+// captured graphs) advance each instance through its own protocol.
 struct RunDev {
   int64_t t;          // step the next field pass evaluates (-1: no field)
   int64_t t_end;      // run stops before this step
@@ -81,10 +89,19 @@ void launch_neighbour_fill(const double* x, const double* y, const double* mx, c
                            const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,
                            double cut2, double alpha, int32_t D, int32_t* col, double* A,
                            double* B, double* Br, hipStream_t st);
+// Grid-wide field pass for every active instance of the table.
 void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,
                   const int32_t* blk_row0, int64_t nblocks, hipStream_t st);
+// One workgroup per instance: relax the current step.
 void launch_relax(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
                   size_t lds_bytes, hipStream_t st);
+// One workgroup per instance: up to max_steps whole steps (field phase and
+// relax) per instance, stopping early once budget_ticks of the device's
+// constant-rate clock have passed (0: no budget).  With first_ready the
+// fields of each instance's first step were already computed.
+void launch_fused(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
+                  size_t lds_bytes, int64_t max_steps, int64_t budget_ticks,
+                  int32_t first_ready, hipStream_t st);
 void launch_set_run(RunDev* run, int64_t t, int64_t t_end, int32_t active, int32_t reset_log,
                     int64_t cur_step, hipStream_t st);
 size_t relax_lds_bytes(int64_t n, int32_t l1_shift);

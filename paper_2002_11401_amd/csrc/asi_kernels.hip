@@ -16,6 +16,8 @@
 //                           flippable keys (ties: lowest index), flip, update
 //                           the neighbours' fields incrementally, repeat
 //                           until none can flip (Sec. II.H)
+//   k_fused                 one workgroup per instance runs whole steps
+//                           (field phase + relax) through its own protocol
 #include <climits>
 
 #include "asi_internal.h"
@@ -248,11 +250,102 @@ __global__ void k_nb_fill(const double* __restrict__ x, const double* __restrict
   }
 }
 
-// ------------------------------------------------------------ full-field pass
-// One lane per magnet.  Dipolar sum of Eq. 3 over the neighbours in
-// ascending order (one accumulator per axis, left to right), then
-// h = h_dip + H[t] + h_th projected (Eq. 2), then the switching key.
-// Each wavefront also writes the maximum key of its 64 rows.
+// ------------------------------------------------------------ field phase
+// Field of row i at step t (Eq. 2): the dipolar sum of Eq. 3 -- gathered over
+// the neighbours in ascending order with one accumulator per axis, left to
+// right, or carried from earlier steps -- plus H[t] and the thermal draw,
+// projected on the easy and hard axis; then the switching key.  Writes the
+// row's total field and key and returns (key, index | sign bit).  Every
+// field pass (grid-wide or inside a fused workgroup) calls this one
+// function, so they agree bit for bit.
+__device__ inline double field_row(const InstDev* __restrict__ I, int64_t i, int64_t t,
+                                   uint32_t& payload) {
+  const int8_t* __restrict__ s = I->s;
+  const int32_t mode = I->field_mode;
+  double p, pq;
+  if (mode == kFieldFull || I->dirty[i]) {
+    const int32_t L = I->len[i];
+    const int64_t base = slot_of(i, I->D, 0);
+    const int32_t* __restrict__ col = I->col + base;
+    const double* __restrict__ A = I->A + base;
+    const double* __restrict__ B = I->B + base;
+    // Chunks of 8 neighbours; the columns of the next chunk are fetched with
+    // the couplings and spins of the current one, so each chunk costs one
+    // round trip.  Accumulation stays in ascending neighbour order.
+    p = 0.0;
+    pq = 0.0;
+    int32_t jc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) jc[u] = (u < L) ? col[u * kSlice] : 0;
+    for (int32_t k = 0; k < L; k += 8) {
+      double a[8], b[8];
+      int sg[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool ok = k + u < L;
+        a[u] = ok ? A[(k + u) * kSlice] : 0.0;
+        b[u] = ok ? B[(k + u) * kSlice] : 0.0;
+        sg[u] = ok ? s[jc[u]] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) jc[u] = (k + 8 + u < L) ? col[(k + 8 + u) * kSlice] : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (k + u < L) {
+          p += (sg[u] > 0) ? a[u] : -a[u];
+          pq += (sg[u] > 0) ? b[u] : -b[u];
+        }
+      }
+    }
+    if (mode != kFieldFull) {
+      I->hd_par[i] = p;
+      I->hd_perp[i] = pq;
+      I->dirty[i] = 0;
+    }
+  } else {
+    // carried, or no neighbour flipped since the last gather
+    p = I->hd_par[i];
+    pq = I->hd_perp[i];
+  }
+  const double mxi = I->mx[i], myi = I->my[i];
+  double hp = p, hq = pq;
+  if (t >= 0) {
+    const double Hx = I->H[2 * t], Hy = I->H[2 * t + 1];
+    hp = hp + (Hx * mxi + Hy * myi);
+    hq = hq + (Hy * mxi - Hx * myi);
+    if (I->sigma > 0.0) {
+      double z0, z1;
+      thermal_normals(I->seed, (uint32_t)i, (uint32_t)t, z0, z1);
+      const double tx = I->sigma * z0, ty = I->sigma * z1;
+      hp = hp + (tx * mxi + ty * myi);
+      hq = hq + (ty * mxi - tx * myi);
+    }
+  }
+  I->h_par[i] = hp;
+  I->h_perp[i] = hq;
+  const int si = s[i];
+  const double key = switching_key(si, hp, hq, I->hk[i], I->b, I->c, I->e_par, I->e_perp);
+  I->key[i] = key;
+  payload = (uint32_t)i | (si < 0 ? 0x80000000u : 0u);
+  return key;
+}
+
+// Field phase for the 64 rows starting at row0 (a multiple of 64), by one
+// wavefront: rows, then their maximum key into the per-64-row table.
+__device__ inline void field_rows64(const InstDev* __restrict__ I, int64_t row0, int64_t t) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = row0 + lane;
+  double key = 0.0;
+  uint32_t payload = 0;
+  if (i < I->n) key = field_row(I, i, t, payload);
+  wave_argmax(key, payload);
+  if (lane == 0) {
+    I->t1key[row0 >> 6] = key;
+    I->t1idx[row0 >> 6] = payload;
+  }
+}
+
+// Grid-wide field pass: one lane per magnet, any number of instances.
 __global__ __launch_bounds__(kFieldBlock) void k_field(const InstDev* __restrict__ insts,
                                                       RunDev* __restrict__ runs,
                                                       const int32_t* __restrict__ blk_inst,
@@ -261,89 +354,9 @@ __global__ __launch_bounds__(kFieldBlock) void k_field(const InstDev* __restrict
   const RunDev* R = runs + q;
   if (!R->active) return;
   const InstDev* I = insts + q;
-  const int64_t n = I->n;
-  const int64_t row0 = blk_row0[blockIdx.x];
-  const int64_t i = row0 + threadIdx.x;
-  const int64_t wave_row0 = row0 + (threadIdx.x & ~63);
-  if (wave_row0 >= n) return;  // whole wavefront past the end
-  const int64_t t = R->t;
-  const int32_t D = I->D;
-  const int8_t* __restrict__ s = I->s;
-
-  double key = 0.0;
-  uint32_t payload = 0;
-  if (i < n) {
-    double p = 0.0, pq = 0.0;
-    const bool gather = I->full_pass || I->dirty[i];
-    if (gather) {
-      const int32_t L = I->len[i];
-      const int64_t base = slot_of(i, D, 0);
-      const int32_t* __restrict__ col = I->col + base;
-      const double* __restrict__ A = I->A + base;
-      const double* __restrict__ B = I->B + base;
-      // Chunks of 8 neighbours; the columns of the next chunk are fetched
-      // with the couplings and spins of the current one, so each chunk costs
-      // one round trip.  Accumulation stays in ascending neighbour order.
-      int32_t jc[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) jc[u] = (u < L) ? col[u * kSlice] : 0;
-      for (int32_t k = 0; k < L; k += 8) {
-        double a[8], b[8];
-        int sg[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const bool ok = k + u < L;
-          a[u] = ok ? A[(k + u) * kSlice] : 0.0;
-          b[u] = ok ? B[(k + u) * kSlice] : 0.0;
-          sg[u] = ok ? s[jc[u]] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) jc[u] = (k + 8 + u < L) ? col[(k + 8 + u) * kSlice] : 0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (k + u < L) {
-            p += (sg[u] > 0) ? a[u] : -a[u];
-            pq += (sg[u] > 0) ? b[u] : -b[u];
-          }
-        }
-      }
-      if (!I->full_pass) {
-        I->hd_par[i] = p;
-        I->hd_perp[i] = pq;
-        I->dirty[i] = 0;
-      }
-    } else {
-      // no neighbour flipped since the last gather: the canonical sum is
-      // unchanged bit for bit
-      p = I->hd_par[i];
-      pq = I->hd_perp[i];
-    }
-    const double mxi = I->mx[i], myi = I->my[i];
-    double hp = p, hq = pq;
-    if (t >= 0) {
-      const double Hx = I->H[2 * t], Hy = I->H[2 * t + 1];
-      hp = hp + (Hx * mxi + Hy * myi);
-      hq = hq + (Hy * mxi - Hx * myi);
-      if (I->sigma > 0.0) {
-        double z0, z1;
-        thermal_normals(I->seed, (uint32_t)i, (uint32_t)t, z0, z1);
-        const double tx = I->sigma * z0, ty = I->sigma * z1;
-        hp = hp + (tx * mxi + ty * myi);
-        hq = hq + (ty * mxi - tx * myi);
-      }
-    }
-    I->h_par[i] = hp;
-    I->h_perp[i] = hq;
-    const int si = s[i];
-    key = switching_key(si, hp, hq, I->hk[i], I->b, I->c, I->e_par, I->e_perp);
-    I->key[i] = key;
-    payload = (uint32_t)i | (si < 0 ? 0x80000000u : 0u);
-  }
-  wave_argmax(key, payload);
-  if ((threadIdx.x & 63) == 0) {
-    I->t1key[wave_row0 >> 6] = key;
-    I->t1idx[wave_row0 >> 6] = payload;
-  }
+  const int64_t wave_row0 = (int64_t)blk_row0[blockIdx.x] + (threadIdx.x & ~63);
+  if (wave_row0 >= I->n) return;  // whole wavefront past the end
+  field_rows64(I, wave_row0, R->t);
 }
 
 // ------------------------------------------------------------ relax
@@ -381,22 +394,22 @@ __device__ inline RelaxLds carve(unsigned char* base, int nt1, int nt2) {
   return L;
 }
 
-// One workgroup relaxes one instance at its current step.  The flippable
-// keys are kept in a three-level max tree: the key array in HBM, first-level
-// tiles of 2^l1_shift magnets and second-level groups of 64 tiles in LDS.
-// Per flip: the root gives j; thread 0 flips it and logs it; every thread
-// updates some of j's neighbours (fields += 2 s_new * coupling, new key);
-// the touched tiles and groups are rescanned.
-__global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __restrict__ insts,
-                                                              RunDev* __restrict__ runs) {
-  RunDev* R = runs + blockIdx.x;
-  if (!R->active) return;
-  const InstDev* I = insts + blockIdx.x;
-  extern __shared__ unsigned char lds_raw[];
-  __shared__ int sh_n1, sh_n2;
-  __shared__ double sh_key;
-  __shared__ uint32_t sh_pay;
+struct RelaxShared {
+  int n1, n2;
+  double key;
+  uint32_t pay;
+};
 
+// Relax one instance at step t with the whole workgroup (Sec. II.H).  The
+// flippable keys are kept in a three-level max tree: the key array in
+// memory, first-level tiles of 2^l1_shift magnets and second-level groups of
+// 64 tiles in LDS, built from the per-64-row maxima of the field phase.
+// Per flip: the root gives j; thread 0 flips it and logs it; the threads
+// update j's neighbours (dipolar and total field += 2 s_new * coupling, new
+// key); the touched tiles and groups are rescanned.  Thread 0 then advances
+// the run cursor.  Returns the relax status (0 or ASI_ELOOP).
+__device__ int relax_step(const InstDev* __restrict__ I, RunDev* __restrict__ R, int64_t t,
+                          unsigned char* lds_raw, RelaxShared& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int NT = blockDim.x, NW = NT >> 6;
   const int64_t n = I->n;
@@ -408,7 +421,6 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
   const int seg = 1 << (l1s - 6);   // magnets per lane in a tile rescan
   RelaxLds L = carve(lds_raw, nt1, nt2);
 
-  // local copies of the instance description
   const int32_t D = I->D;
   const int32_t* __restrict__ colp = I->col;
   const double* __restrict__ Ap = I->A;
@@ -417,13 +429,15 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
   int8_t* __restrict__ sp = I->s;
   double* __restrict__ hpp = I->h_par;
   double* __restrict__ hqp = I->h_perp;
+  double* __restrict__ hdp = I->hd_par;
+  double* __restrict__ hdq = I->hd_perp;
   double* __restrict__ keyp = I->key;
   uint8_t* __restrict__ dirtyp = I->dirty;
+  const int32_t mode = I->field_mode;
   const double pb = I->b, pc = I->c, ep = I->e_par, eq = I->e_perp;
   const int64_t max_flips = I->max_flips;
-  const int64_t t = R->t;
 
-  // first level from the per-64-row maxima of the field pass
+  // first level from the per-64-row maxima of the field phase
   for (int e = tid; e < nt1; e += NT) {
     double bk = 0.0;
     uint32_t bi = 0;
@@ -442,8 +456,8 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
     L.l1flag[e] = 0;
   }
   if (tid == 0) {
-    sh_n1 = 0;
-    sh_n2 = 0;
+    sh.n1 = 0;
+    sh.n2 = 0;
   }
   __syncthreads();
   for (int g = wave; g < nt2; g += NW) {
@@ -481,13 +495,13 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
       }
       wave_argmax(bk, bp);
       if (lane == 0) {
-        sh_key = bk;
-        sh_pay = bp;
+        sh.key = bk;
+        sh.pay = bp;
       }
     }
     __syncthreads();
-    const double top = sh_key;
-    const uint32_t pay = sh_pay;
+    const double top = sh.key;
+    const uint32_t pay = sh.pay;
     if (!(top > 0.0)) break;
     if (flips >= max_flips) {
       status = -5;
@@ -505,7 +519,7 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
       const uint64_t w = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)j;
       hash = (hash ^ w) * 0x100000001b3ull;
       const int e = (int)(j >> l1s);
-      if (atomicExch(&L.l1flag[e], 1) == 0) L.l1list[atomicAdd(&sh_n1, 1)] = e;
+      if (atomicExch(&L.l1flag[e], 1) == 0) L.l1list[atomicAdd(&sh.n1, 1)] = e;
     }
     ++logpos;
     ++flips;
@@ -514,21 +528,26 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
       const int64_t sl = slot_of(j, D, k);
       const int32_t i = colp[sl];
       if (i >= 0) {
-        const double a = Ap[sl], br = Brp[sl];
-        const double hp = hpp[i] + two * a;
-        const double hq = hqp[i] + two * br;
+        const double da = two * Ap[sl], db = two * Brp[sl];
+        const double hp = hpp[i] + da;
+        const double hq = hqp[i] + db;
+        if (mode == kFieldCarry) {
+          hdp[i] = hdp[i] + da;
+          hdq[i] = hdq[i] + db;
+        } else if (mode == kFieldDirty) {
+          dirtyp[i] = 1;
+        }
         const int si = sp[i];
         const double kk = switching_key(si, hp, hq, hkp[i], pb, pc, ep, eq);
         hpp[i] = hp;
         hqp[i] = hq;
         keyp[i] = kk;
-        dirtyp[i] = 1;
         const int e = (int)(i >> l1s);
-        if (atomicExch(&L.l1flag[e], 1) == 0) L.l1list[atomicAdd(&sh_n1, 1)] = e;
+        if (atomicExch(&L.l1flag[e], 1) == 0) L.l1list[atomicAdd(&sh.n1, 1)] = e;
       }
     }
     __syncthreads();
-    const int n1 = sh_n1;
+    const int n1 = sh.n1;
     for (int u = wave; u < n1; u += NW) {
       const int e = L.l1list[u];
       const int64_t r0 = ((int64_t)e << l1s) + (int64_t)lane * seg;
@@ -551,12 +570,12 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
         L.l1i[e] = bp;
         L.l1flag[e] = 0;
         const int g = e / kL2Group;
-        if (atomicExch(&L.l2flag[g], 1) == 0) L.l2list[atomicAdd(&sh_n2, 1)] = g;
+        if (atomicExch(&L.l2flag[g], 1) == 0) L.l2list[atomicAdd(&sh.n2, 1)] = g;
       }
     }
     __syncthreads();
-    if (tid == 0) sh_n1 = 0;
-    const int n2 = sh_n2;
+    if (tid == 0) sh.n1 = 0;
+    const int n2 = sh.n2;
     for (int u = wave; u < n2; u += NW) {
       const int g = L.l2list[u];
       const int e = g * kL2Group + lane;
@@ -570,7 +589,7 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
       }
     }
     __syncthreads();
-    if (tid == 0) sh_n2 = 0;
+    if (tid == 0) sh.n2 = 0;
   }
   if (tid == 0) {
     R->flips += flips;
@@ -581,6 +600,53 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
     R->t = t + 1;
     if (status != 0) R->status = status;
     R->active = (status == 0 && R->t < R->t_end) ? 1 : 0;
+  }
+  __syncthreads();
+  return status;
+}
+
+__global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __restrict__ insts,
+                                                              RunDev* __restrict__ runs) {
+  RunDev* R = runs + blockIdx.x;
+  if (!R->active) return;
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ RelaxShared sh;
+  relax_step(insts + blockIdx.x, R, R->t, lds_raw, sh);
+}
+
+// One workgroup per instance runs whole field steps -- its own field phase,
+// wavefront by wavefront, then the relax -- through its own protocol, so
+// instances never wait for each other between steps.  Stops after max_steps
+// steps, at the end of the protocol, on ELOOP, or once budget_ticks of the
+// constant-rate device clock have passed (checked between steps).
+__global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_fused(const InstDev* __restrict__ insts,
+                                                              RunDev* __restrict__ runs,
+                                                              int64_t max_steps,
+                                                              int64_t budget_ticks,
+                                                              int32_t first_ready) {
+  RunDev* R = runs + blockIdx.x;
+  if (!R->active) return;
+  const InstDev* I = insts + blockIdx.x;
+  extern __shared__ unsigned char lds_raw[];
+  __shared__ RelaxShared sh;
+  __shared__ int go;
+  const int wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
+  const uint64_t t_start = wall_clock64();
+  bool ready = first_ready != 0;
+  for (int64_t k = 0; k < max_steps; ++k) {
+    const int64_t t = R->t;
+    if (!ready) {
+      for (int64_t row0 = (int64_t)wave * 64; row0 < I->n; row0 += (int64_t)NW * 64)
+        field_rows64(I, row0, t);
+      __syncthreads();
+    }
+    ready = false;
+    if (relax_step(I, R, t, lds_raw, sh) != 0) break;
+    if (threadIdx.x == 0)
+      go = (R->active && (budget_ticks <= 0 ||
+                          (int64_t)(wall_clock64() - t_start) < budget_ticks)) ? 1 : 0;
+    __syncthreads();
+    if (!go) break;
   }
 }
 
@@ -637,6 +703,14 @@ void launch_relax(const InstDev* insts, RunDev* runs, int32_t count, int32_t wav
   if (count <= 0) return;
   hipLaunchKernelGGL(k_relax, dim3((unsigned)count), dim3(64 * waves), lds_bytes, st, insts,
                      runs);
+}
+
+void launch_fused(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
+                  size_t lds_bytes, int64_t max_steps, int64_t budget_ticks,
+                  int32_t first_ready, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fused, dim3((unsigned)count), dim3(64 * waves), lds_bytes, st, insts, runs,
+                     max_steps, budget_ticks, first_ready);
 }
 
 void launch_set_run(RunDev* run, int64_t t, int64_t t_end, int32_t active, int32_t reset_log,

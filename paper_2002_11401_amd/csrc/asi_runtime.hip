@@ -217,8 +217,8 @@ asi_status validate(const asi_params* p) {
     return fail(ASI_EINVAL, "thermal_std must be finite and >= 0");
   if (p->max_flips_per_step < 0 || p->flip_log_capacity < 0)
     return fail(ASI_EINVAL, "negative cap");
-  if (p->full_field_pass != 0 && p->full_field_pass != 1)
-    return fail(ASI_EINVAL, "full_field_pass must be 0 or 1");
+  if (p->field_mode < 0 || p->field_mode > 2)
+    return fail(ASI_EINVAL, "field_mode must be 0, 1 or 2");
   for (int64_t i = 0; i < p->n; ++i) {
     if (!std::isfinite(p->xy[2 * i]) || !std::isfinite(p->xy[2 * i + 1]) ||
         !std::isfinite(p->theta[i]))
@@ -390,7 +390,7 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   I.H = nullptr;
   I.K = 0;
   I.s = ds;
-  I.full_pass = p->full_field_pass ? 1 : 0;
+  I.field_mode = p->field_mode;
   I.dirty = dalloc<uint8_t>(s, n);
   I.hd_par = dalloc<double>(s, n);
   I.hd_perp = dalloc<double>(s, n);
@@ -413,6 +413,9 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
       !I.log_t || !I.log_j || !s->dI || !s->dR || !s->blk_inst || !s->blk_row0)
     return fail(ASI_ENOMEM, "device allocation failed (state)");
   HIPCHK(hipMemsetAsync(I.h_par, 0, 8 * n, s->stream), s);
+  HIPCHK(hipMemsetAsync(I.h_perp, 0, 8 * n, s->stream), s);
+  HIPCHK(hipMemsetAsync(I.hd_par, 0, 8 * n, s->stream), s);
+  HIPCHK(hipMemsetAsync(I.hd_perp, 0, 8 * n, s->stream), s);
   HIPCHK(hipMemsetAsync(I.dirty, 1, n, s->stream), s);
   HIPCHK(hipMemsetAsync(I.h_perp, 0, 8 * n, s->stream), s);
   std::vector<int32_t> bi(s->nblocks, 0), br(s->nblocks);
@@ -739,9 +742,10 @@ asi_status table_capture(Table& T, hipStream_t st) {
 
 }  // namespace
 
-extern "C" asi_status asi_batch_run(asi_handle* hs, int32_t count, int32_t use_graph,
+extern "C" asi_status asi_batch_run(asi_handle* hs, int32_t count, int32_t mode,
                                     int64_t* flips_out) {
   if (!hs || count < 1) return fail(ASI_EINVAL, "no handles");
+  if (mode < 0 || mode > 2) return fail(ASI_EINVAL, "batch mode must be 0, 1 or 2");
   for (int32_t k = 0; k < count; ++k) {
     asi_status st = check_handle(hs[k]);
     if (st != ASI_OK) return st;
@@ -780,17 +784,19 @@ extern "C" asi_status asi_batch_run(asi_handle* hs, int32_t count, int32_t use_g
                                     hipMemcpyHostToDevice, st);
       if (e != hipSuccess) res = fail(ASI_EDEVICE, hipGetErrorString(e));
     }
-    if (res == ASI_OK && use_graph && max_steps > 0) res = table_capture(T, st);
-    if (res == ASI_OK) {
-      for (int64_t s = 0; s < max_steps; ++s) {
-        if (T.exec) {
-          hipError_t e = hipGraphLaunch(T.exec, st);
-          if (e != hipSuccess) {
-            res = fail(ASI_EDEVICE, hipGetErrorString(e));
-            break;
+    if (res == ASI_OK && max_steps > 0) {
+      if (mode == 2) {
+        launch_field(T.dI, T.dR, T.blk_inst, T.blk_row0, T.nblocks, st);
+        launch_fused(T.dI, T.dR, T.count, T.waves, T.lds, max_steps, 0, 1, st);
+      } else {
+        if (mode == 1) res = table_capture(T, st);
+        for (int64_t s = 0; res == ASI_OK && s < max_steps; ++s) {
+          if (T.exec) {
+            hipError_t e = hipGraphLaunch(T.exec, st);
+            if (e != hipSuccess) res = fail(ASI_EDEVICE, hipGetErrorString(e));
+          } else {
+            table_step(T, st);
           }
-        } else {
-          table_step(T, st);
         }
       }
     }
@@ -891,6 +897,7 @@ struct asi_server {
   Table T;
   bool dirty = true;
   std::vector<RunDev> runs;
+  int64_t clock_hz = 100000000;  // device constant-rate clock
 };
 
 namespace {
@@ -940,6 +947,13 @@ asi_status asi_server_create(const asi_device* dev, size_t hbm_budget_bytes, int
   S->slots.assign(max_slots, -1);
   S->runs.assign(max_slots, RunDev{});
   S->T.mem.dev = S->dev;
+  {
+    int dev_id = 0, khz = 0;
+    if (hipGetDevice(&dev_id) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev_id) == hipSuccess &&
+        khz > 0)
+      S->clock_hz = (int64_t)khz * 1000;
+  }
   *out = S;
   return ASI_OK;
 }
@@ -968,8 +982,9 @@ asi_status asi_server_submit(asi_server_t S, const asi_params* p, int64_t n_step
   return ASI_OK;
 }
 
-asi_status asi_server_step(asi_server_t S, int32_t* active_out) {
+asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out) {
   if (!S) return fail(ASI_EINVAL, "null server");
+  if (!(budget_ms > 0.0)) return fail(ASI_EINVAL, "budget_ms must be > 0");
   // admit in arrival order while a slot and the budget allow
   while (!S->queue.empty()) {
     int32_t slot = -1;
@@ -1019,7 +1034,12 @@ asi_status asi_server_step(asi_server_t S, int32_t* active_out) {
       asi_status st = server_rebuild(S);
       if (st != ASI_OK) return st;
     }
-    table_step(S->T, S->stream);
+    // one field launch (neighbour gathers of new jobs run grid-wide here),
+    // then every resident job advances through its own steps
+    const int64_t ticks = (int64_t)(budget_ms * 1e-3 * (double)S->clock_hz);
+    launch_field(S->T.dI, S->T.dR, S->T.blk_inst, S->T.blk_row0, S->T.nblocks, S->stream);
+    launch_fused(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, INT64_MAX, ticks, 1,
+                 S->stream);
     HIPCHK(hipMemcpyAsync(S->runs.data(), S->T.dR, sizeof(RunDev) * S->max_slots,
                           hipMemcpyDeviceToHost, S->stream),
            (asi_sim*)nullptr);

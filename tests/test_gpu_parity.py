@@ -164,17 +164,20 @@ def test_kagome1m_sampled_windows_bit_exact():
 
 
 # ------------------------------------------------------------------ invariances
-def test_checkpoint_resume_bitwise():
+@pytest.mark.parametrize("mode", ["dirty", "full"])
+def test_checkpoint_resume_bitwise(mode):
+    """With re-gathered (canonical) fields the state at a step boundary is the
+    spins alone, so a resumed run is bitwise identical."""
     w = W.square_10x10_triangle()
-    say("checkpoint/resume")
-    a = gpu_sim(w)
+    say("checkpoint/resume", mode)
+    a = gpu_sim(w, field_mode=mode)
     a.run(0, 120)
     s_mid, _, _, step = a.state()
     assert step == 119
     log_a = a.flip_log()
     a.run(120, w.n_steps)
     full = a.flip_log()
-    b = gpu_sim(w)
+    b = gpu_sim(w, field_mode=mode)
     b.set_state(s_mid, step)
     b.run(120, w.n_steps)
     lb = b.flip_log()
@@ -182,6 +185,7 @@ def test_checkpoint_resume_bitwise():
     assert np.array_equal(lb["idx"], full["idx"][k:])
     assert np.array_equal(lb["step"], full["step"][k:])
     assert np.array_equal(a.state()[0], b.state()[0])
+    assert np.array_equal(a.state()[1], b.state()[1])
 
 
 def test_relax_is_idempotent_and_zero_field_step():
@@ -201,9 +205,10 @@ def test_batched_equals_plain_bitwise():
         s = gpu_sim(w)
         s.run()
         plain.append((s.flip_log(), s.state()))
-    for use_graph in (False, True):
+    for mode in ("lockstep", "graph", "fused"):
+        say("batch mode", mode)
         sims = [gpu_sim(w) for w in ws]
-        flips = asi.batch_run(sims, use_graph=use_graph)
+        flips = asi.batch_run(sims, mode=mode)
         for k, s in enumerate(sims):
             lg = s.flip_log()
             assert flips[k] == lg["count"] == plain[k][0]["count"]
@@ -288,7 +293,7 @@ def test_small_log_capacity_keeps_counting():
     assert lg["hash"] == asi.flip_hash(r["step"], r["idx"])
 
 
-def test_full_pass_and_dirty_row_modes_bitwise():
+def test_full_pass_and_dirty_row_modes_bitwise():  # noqa: D103
     """Re-gathering only rows with a flipped neighbour gives the same bits as
     a full-field pass every step (fields, flips, spins), and both match the
     oracle."""
@@ -299,8 +304,8 @@ def test_full_pass_and_dirty_row_modes_bitwise():
                    W.disorder_hk(n, 0.15, 0.05, 8), H, alpha=0.002, neighbor_distance=3.0,
                    b=1, c=1, beta=3, gamma=3, thermal_std=0.005, thermal_seed=4)
     say("full vs dirty-row field pass", n)
-    a = gpu_sim(w, full_field_pass=True)
-    b = gpu_sim(w)
+    a = gpu_sim(w, field_mode="full")
+    b = gpu_sim(w, field_mode="dirty")
     for t0, t1 in [(0, 40), (40, 41), (41, 120)]:
         a.run(t0, t1)
         b.run(t0, t1)
@@ -311,3 +316,35 @@ def test_full_pass_and_dirty_row_modes_bitwise():
     assert la["hash"] == lb["hash"] and la["count"] == lb["count"] > 0
     o, r = oracle_run(w)
     assert_same_flips(lb, r, b.state()[0], o.spins())
+
+
+@pytest.mark.parametrize("mode", ["carry", "dirty"])
+def test_fused_batch_thermal_bitwise_and_oracle(mode):
+    """Fused persistent batch (each instance's workgroup runs its own field
+    phases and relaxes) with thermal noise: bitwise equal to plain runs, and
+    flip-exact against the oracle."""
+    ws = []
+    for k, cells in enumerate((5, 9, 14, 20)):
+        xy, theta = W.kagome(cells)
+        n = len(theta)
+        H = W.rotating(60 + 10 * k, 0.08, 40)
+        ws.append(W.Workload(f"kagome{cells}", xy, theta, W.polarised_spins(theta, H[0]),
+                             W.disorder_hk(n, 0.15, 0.05, 20 + k), H, alpha=0.002,
+                             neighbor_distance=3.0, b=1, c=1, beta=3, gamma=3,
+                             thermal_std=0.006, thermal_seed=30 + k))
+    say("fused thermal batch", mode, [w.n for w in ws])
+    plain = []
+    for w in ws:
+        s = gpu_sim(w, field_mode=mode)
+        s.run()
+        plain.append((s.flip_log(), s.state()))
+    sims = [gpu_sim(w, field_mode=mode) for w in ws]
+    asi.batch_run(sims, mode="fused")
+    for k, (s, w) in enumerate(zip(sims, ws)):
+        lg = s.flip_log()
+        st = s.state()
+        assert lg["hash"] == plain[k][0]["hash"] and lg["count"] == plain[k][0]["count"]
+        for x, y in zip(st[:3], plain[k][1][:3]):
+            assert np.array_equal(x, y)
+        o, r = oracle_run(w)
+        assert_same_flips(lg, r, st[0], o.spins())
