@@ -65,6 +65,15 @@ struct InstDev {
   int64_t log_cap;
   int32_t* step_flips;    // [K] flips of each step (may be null)
   int64_t max_flips;      // per relax
+  // candidate pool of the speculative relax: the field phase appends every
+  // flippable magnet as (key, index | sign bit, version) to buffer 0
+  uint32_t* ver;          // [n] version of each magnet's key
+  uint32_t* cpay[2];      // [ccap] pool buffers
+  double* ckey[2];
+  uint32_t* cver[2];
+  int32_t* ccount;        // entries in buffer 0 (field phase appends)
+  int64_t ccap;
+  int64_t spec_min;       // flippable magnets at step start to go speculative
 };
 
 // Per-instance run cursor, device-resident so repeated launches (and
@@ -104,7 +113,10 @@ void launch_fused(const InstDev* insts, RunDev* runs, int32_t count, int32_t wav
                   int32_t first_ready, hipStream_t st);
 void launch_set_run(RunDev* run, int64_t t, int64_t t_end, int32_t active, int32_t reset_log,
                     int64_t cur_step, hipStream_t st);
+// Dynamic LDS of the relax and fused kernels for an instance of n magnets.
 size_t relax_lds_bytes(int64_t n, int32_t l1_shift);
 int32_t relax_l1_shift(int64_t n);
+// Raise the dynamic-LDS limit of the relax kernels (call once per process).
+hipError_t configure_kernels();
 
 }  // namespace asi

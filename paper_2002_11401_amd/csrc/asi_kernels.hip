@@ -258,7 +258,7 @@ __global__ void k_nb_fill(const double* __restrict__ x, const double* __restrict
 // row's total field and key and returns (key, index | sign bit).  Every
 // field pass (grid-wide or inside a fused workgroup) calls this one
 // function, so they agree bit for bit.
-__device__ inline double field_row(const InstDev* __restrict__ I, int64_t i, int64_t t,
+__device__ __forceinline__ double field_row(const InstDev* __restrict__ I, int64_t i, int64_t t,
                                    uint32_t& payload) {
   const int8_t* __restrict__ s = I->s;
   const int32_t mode = I->field_mode;
@@ -332,12 +332,25 @@ __device__ inline double field_row(const InstDev* __restrict__ I, int64_t i, int
 
 // Field phase for the 64 rows starting at row0 (a multiple of 64), by one
 // wavefront: rows, then their maximum key into the per-64-row table.
-__device__ inline void field_rows64(const InstDev* __restrict__ I, int64_t row0, int64_t t) {
+__device__ __forceinline__ void field_rows64(const InstDev* __restrict__ I, int64_t row0, int64_t t) {
   const int lane = threadIdx.x & 63;
   const int64_t i = row0 + lane;
   double key = 0.0;
   uint32_t payload = 0;
   if (i < I->n) key = field_row(I, i, t, payload);
+  // append the flippable rows to the candidate pool (one atomic per wave)
+  const unsigned long long bal = __ballot(key > 0.0);
+  if (bal) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(I->ccount, __popcll(bal));
+    base = __builtin_amdgcn_readfirstlane(base);
+    if (key > 0.0) {
+      const int64_t q = base + __popcll(bal & ((1ull << lane) - 1ull));
+      I->cpay[0][q] = payload;
+      I->ckey[0][q] = key;
+      I->cver[0][q] = I->ver[i];
+    }
+  }
   wave_argmax(key, payload);
   if (lane == 0) {
     I->t1key[row0 >> 6] = key;
@@ -373,6 +386,21 @@ struct RelaxLds {
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
+__host__ __device__ inline size_t relax_tree_lds_bytes(int64_t n, int32_t l1_shift) {
+  const int64_t nt1 = (n + (1LL << l1_shift) - 1) >> l1_shift;
+  const int64_t nt2 = (nt1 + kL2Group - 1) / kL2Group;
+  size_t off = 0;
+  off = align16(off + sizeof(double) * nt1);
+  off = align16(off + sizeof(uint32_t) * nt1);
+  off = align16(off + sizeof(int32_t) * nt1);
+  off = align16(off + sizeof(int32_t) * nt1);
+  off = align16(off + sizeof(double) * nt2);
+  off = align16(off + sizeof(uint32_t) * nt2);
+  off = align16(off + sizeof(int32_t) * nt2);
+  off = align16(off + sizeof(int32_t) * nt2);
+  return off;
+}
+
 __device__ inline RelaxLds carve(unsigned char* base, int nt1, int nt2) {
   RelaxLds L;
   size_t off = 0;
@@ -400,16 +428,554 @@ struct RelaxShared {
   uint32_t pay;
 };
 
+// ------------------------------------------------------------ speculative relax
+// Exact-order batched relax for steps that start with many flippable
+// magnets.  Candidates live in a pool in memory (filled by the field phase)
+// and a hot window in LDS that is sorted best first (largest key, then lowest
+// index).  Entries are (key, index | sign bit, version); an entry is valid
+// while its version equals the magnet's version counter, which every change
+// of the magnet's key bumps.  Every valid pool entry is no better than
+// cold_max, so window entries better than cold_max can be taken in order.
+//
+// A batch takes the first B safe window entries c_1 .. c_B and flips the
+// longest prefix c_1 .. c_p that the one-at-a-time relax would flip in the
+// same order: the members and their neighbour sets are pairwise disjoint
+// (so no member's field or key depends on an earlier member of the prefix,
+// and every touched magnet gets exactly one update), and no touched magnet's
+// new key beats a later member of the prefix.  Then c_m is the argmax after
+// c_1 .. c_{m-1} for every m <= p, and applying the prefix together gives
+// the same flips, log, fields and keys, bit for bit.
+constexpr int kWin = 2048;        // hot window entries
+constexpr int kHash = 4096;       // conflict table slots
+constexpr int kMaxPairs = 2048;   // member + neighbour slots per batch
+constexpr int kMaxMembers = 64;
+constexpr int kSpecMaxD = 128;    // above this degree batches are too short to pay
+
+// Relax order of two magnets: larger key first, then lower index.
+__device__ inline bool better(double ka, uint32_t pa, double kb, uint32_t pb) {
+  return ka > kb || (ka == kb && (pa & 0x7fffffffu) < (pb & 0x7fffffffu));
+}
+
+// Order of pool and window entries: the relax order, then the newer version
+// of the same magnet first, so that no two distinct entries tie.
+__device__ inline bool better_e(double ka, uint32_t pa, uint32_t va, double kb, uint32_t pb,
+                                uint32_t vb) {
+  if (ka != kb) return ka > kb;
+  const uint32_t ia = pa & 0x7fffffffu, ib = pb & 0x7fffffffu;
+  if (ia != ib) return ia < ib;
+  return va > vb;
+}
+
+struct SpecLds {
+  unsigned char* win;  // hot window, two buffers of kWin entries each:
+                       //   buffer b: keys at win + b * kWinBytes, then payloads, versions
+  double* sk;       // staging / sort scratch (aliases the conflict table)
+  uint32_t* sp;
+  uint32_t* sv;
+  uint32_t* hidx;   // conflict table: magnet + 1 (0: empty)
+  int32_t* hown;    //   lowest member rank owning that magnet
+  int32_t* mval;    // per window position: member valid
+  int32_t* mrank;   //   its rank among the valid members (-1: stale)
+  double* mk;       // per rank: key, payload, window position
+  uint32_t* mp;
+  int32_t* mpos;
+};
+
+constexpr size_t kWinBytes = (size_t)kWin * 16;
+__device__ inline double* win_k(const SpecLds& S, int b) {
+  return (double*)(S.win + (size_t)b * kWinBytes);
+}
+__device__ inline uint32_t* win_p(const SpecLds& S, int b) {
+  return (uint32_t*)(S.win + (size_t)b * kWinBytes + sizeof(double) * kWin);
+}
+__device__ inline uint32_t* win_v(const SpecLds& S, int b) {
+  return (uint32_t*)(S.win + (size_t)b * kWinBytes + (sizeof(double) + sizeof(uint32_t)) * kWin);
+}
+
+__host__ __device__ inline size_t spec_lds_bytes() {
+  return 2 * (size_t)kWin * 16 + (size_t)kWin * 16 + (size_t)kMaxMembers * (4 + 4 + 8 + 4 + 4);
+}
+
+__device__ inline SpecLds carve_spec(unsigned char* base) {
+  SpecLds S;
+  S.win = base;
+  size_t off = 2 * kWinBytes;
+  S.sk = (double*)(base + off);
+  S.sp = (uint32_t*)(base + off + sizeof(double) * kWin);
+  S.sv = (uint32_t*)(base + off + (sizeof(double) + sizeof(uint32_t)) * kWin);
+  S.hidx = (uint32_t*)(base + off);
+  S.hown = (int32_t*)(base + off + sizeof(uint32_t) * kHash);
+  off += (size_t)kWin * 16;
+  S.mk = (double*)(base + off);
+  off += sizeof(double) * kMaxMembers;
+  S.mp = (uint32_t*)(base + off);
+  off += sizeof(uint32_t) * kMaxMembers;
+  S.mpos = (int32_t*)(base + off);
+  off += sizeof(int32_t) * kMaxMembers;
+  S.mval = (int32_t*)(base + off);
+  off += sizeof(int32_t) * kMaxMembers;
+  S.mrank = (int32_t*)(base + off);
+  return S;
+}
+
+struct SpecShared {
+  int nx, xb, ns, nvalid, p, safe, cb;
+  int64_t ncold, ncold_out, napp;
+  double cmk;       // cold_max (key, payload, version); key -1: pool empty
+  uint32_t cmp, cmv;
+  double rk;        // best entry a merge discarded into the pool
+  uint32_t rp, rv;
+};
+
+// Block-wide bitonic sort, best first, of P (a power of two) entries.
+__device__ __forceinline__ void bitonic_best_first(double* k, uint32_t* p, uint32_t* v, int P) {
+  const int tid = threadIdx.x, NT = blockDim.x;
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int q = tid; q < P / 2; q += NT) {
+        const int lo = 2 * stride * (q / stride) + (q % stride);
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;  // this segment runs best first
+        const bool sw = up ? better_e(k[hi], p[hi], v[hi], k[lo], p[lo], v[lo])
+                           : better_e(k[lo], p[lo], v[lo], k[hi], p[hi], v[hi]);
+        if (sw) {
+          const double tk = k[lo];
+          k[lo] = k[hi];
+          k[hi] = tk;
+          const uint32_t tp = p[lo];
+          p[lo] = p[hi];
+          p[hi] = tp;
+          const uint32_t tv = v[lo];
+          v[lo] = v[hi];
+          v[hi] = tv;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Number of entries taken from A among the first d outputs of merge(A, B)
+// (both best first; on equal entries A goes first).
+__device__ __forceinline__ int co_rank(int d, const double* ak, const uint32_t* ap,
+                                      const uint32_t* av, int na, const double* bk,
+                                      const uint32_t* bp, const uint32_t* bv, int nb) {
+  int lo = d > nb ? d - nb : 0;
+  int hi = d < na ? d : na;
+  while (lo < hi) {
+    const int i = (lo + hi) >> 1;
+    const int j = d - i;
+    if (j > 0 && i < na && !better_e(bk[j - 1], bp[j - 1], bv[j - 1], ak[i], ap[i], av[i]))
+      lo = i + 1;
+    else
+      hi = i;
+  }
+  return lo;
+}
+
+// Merge A = window[a0, a0+na) with B = staging[0, nb) (both best first):
+// the first `keep` outputs become the window (other buffer), the rest are
+// appended to pool buffer pb at sh.ncold_out; sh.rk/rp keeps the best entry
+// sent to the pool.
+__device__ __forceinline__ void merge_keep(const InstDev* I, const SpecLds& S, SpecShared& sh, int a0, int na,
+                           int nb, int keep, int pb) {
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const int xb = sh.xb;
+  const double* ak = win_k(S, xb) + a0;
+  const uint32_t* ap = win_p(S, xb) + a0;
+  const uint32_t* av = win_v(S, xb) + a0;
+  double* ok = win_k(S, xb ^ 1);
+  uint32_t* op = win_p(S, xb ^ 1);
+  uint32_t* ov = win_v(S, xb ^ 1);
+  uint32_t* pool_p = I->cpay[pb];
+  double* pool_k = I->ckey[pb];
+  uint32_t* pool_v = I->cver[pb];
+  const int total = na + nb;
+  const int per = (total + NT - 1) / NT;
+  const int d0 = tid * per < total ? tid * per : total;
+  const int d1 = d0 + per < total ? d0 + per : total;
+  const int64_t base = sh.ncold_out;
+  if (d0 < d1) {
+    int i = co_rank(d0, ak, ap, av, na, S.sk, S.sp, S.sv, nb);
+    int j = d0 - i;
+    for (int d = d0; d < d1; ++d) {
+      double ek;
+      uint32_t epay, ever;
+      if (j >= nb || (i < na && !better_e(S.sk[j], S.sp[j], S.sv[j], ak[i], ap[i], av[i]))) {
+        ek = ak[i];
+        epay = ap[i];
+        ever = av[i];
+        ++i;
+      } else {
+        ek = S.sk[j];
+        epay = S.sp[j];
+        ever = S.sv[j];
+        ++j;
+      }
+      if (d < keep) {
+        ok[d] = ek;
+        op[d] = epay;
+        ov[d] = ever;
+      } else {
+        const int64_t q = base + (d - keep);
+        pool_k[q] = ek;
+        pool_p[q] = epay;
+        pool_v[q] = ever;
+        if (d == keep && better_e(ek, epay, ever, sh.rk, sh.rp, sh.rv)) {
+          sh.rk = ek;
+          sh.rp = epay;
+          sh.rv = ever;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    sh.ncold_out += total - keep;
+    sh.xb ^= 1;
+    sh.nx = keep;
+  }
+  __syncthreads();
+}
+
+// Sort staging entries [0, ns) best first (padded to a power of two).
+__device__ __forceinline__ void sort_staging(const SpecLds& S, int ns) {
+  int P = 1;
+  while (P < ns) P <<= 1;
+  for (int q = ns + threadIdx.x; q < P; q += blockDim.x) {
+    S.sk[q] = -1.0;
+    S.sp[q] = 0x7fffffffu;
+    S.sv[q] = 0u;
+  }
+  __syncthreads();
+  if (P > 1) bitonic_best_first(S.sk, S.sp, S.sv, P);
+}
+
+// Window := best kWin entries of (window + valid pool entries); the other
+// valid pool entries move to the other pool buffer; cold_max becomes exact.
+__device__ __forceinline__ void refill(const InstDev* I, const SpecLds& S, SpecShared& sh) {
+  const int tid = threadIdx.x, NT = blockDim.x;
+  const int cb = sh.cb;
+  const int64_t ncold = sh.ncold;
+  if (tid == 0) {
+    sh.ncold_out = 0;
+    sh.rk = -1.0;
+    sh.rp = 0x7fffffffu;
+    sh.rv = 0u;
+  }
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < ncold; c0 += kWin) {
+    const int m = (int)(ncold - c0 < kWin ? ncold - c0 : kWin);
+    for (int q = tid; q < m; q += NT) {
+      const uint32_t pay = I->cpay[cb][c0 + q];
+      const uint32_t ver = I->cver[cb][c0 + q];
+      const bool ok = I->ver[pay & 0x7fffffffu] == ver;
+      S.sk[q] = ok ? I->ckey[cb][c0 + q] : -1.0;
+      S.sp[q] = ok ? pay : 0x7fffffffu;
+      S.sv[q] = ver;
+    }
+    __syncthreads();
+    sort_staging(S, m);
+    if (tid == 0) {
+      int lo = 0, hi = m;  // valid entries sort first
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (S.sk[mid] > 0.0) lo = mid + 1; else hi = mid;
+      }
+      sh.ns = lo;
+    }
+    __syncthreads();
+    const int nv = sh.ns;
+    const int nx = sh.nx;
+    const int keep = nx + nv < kWin ? nx + nv : kWin;
+    merge_keep(I, S, sh, 0, nx, nv, keep, cb ^ 1);
+  }
+  if (tid == 0) {
+    sh.cb = cb ^ 1;
+    sh.ncold = sh.ncold_out;
+    sh.cmk = sh.rk;
+    sh.cmp = sh.rp;
+    sh.cmv = sh.rv;
+  }
+  __syncthreads();
+}
+
+// Window entries better than cold_max (all of them when the pool is empty).
+__device__ __forceinline__ int count_safe(const SpecLds& S, const SpecShared& sh) {
+  const int nx = sh.nx;
+  if (sh.ncold == 0) return nx;
+  const double* k = win_k(S, sh.xb);
+  const uint32_t* p = win_p(S, sh.xb);
+  const uint32_t* v = win_v(S, sh.xb);
+  int lo = 0, hi = nx;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (better_e(k[mid], p[mid], v[mid], sh.cmk, sh.cmp, sh.cmv)) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ inline uint32_t hash_slot(uint32_t i) { return (i * 2654435761u) >> (32 - 12); }
+
+// Relax at step t in speculative batches (needs 1024 threads).  flips,
+// logpos and hash are the running counters (logpos and hash significant in
+// thread 0).  Returns 0 or -5 (flip cap reached with a flippable magnet left).
+__device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t t, unsigned char* lds,
+                          SpecShared& sh, int64_t ncand, int64_t& flips, int64_t& logpos,
+                          uint64_t& hash) {
+  constexpr int kPPT = kMaxPairs / 1024;  // pair slots per thread
+  const int tid = threadIdx.x, NT = blockDim.x;
+  SpecLds S = carve_spec(lds);
+  const int32_t D = I->D;
+  const int32_t mode = I->field_mode;
+  const double pb = I->b, pc = I->c, ep = I->e_par, eq = I->e_perp;
+  const int64_t max_flips = I->max_flips;
+  const int PW = D + 1;  // pair slots per member: its neighbours and itself
+  int Bmax = kMaxPairs / PW;
+  if (Bmax > kMaxMembers) Bmax = kMaxMembers;
+  if (tid == 0) {
+    sh.nx = 0;
+    sh.xb = 0;
+    sh.cb = 0;
+    sh.ncold = ncand;
+    sh.cmk = 1e300;  // unknown until the first refill
+    sh.cmp = 0;
+    sh.cmv = 0;
+  }
+  __syncthreads();
+  int status = 0;
+  while (true) {
+    if (tid == 0) sh.safe = count_safe(S, sh);
+    __syncthreads();
+    if (sh.safe == 0 || sh.ncold + kMaxPairs + kWin > I->ccap) {
+      if (sh.ncold == 0 && sh.safe == 0) break;
+      refill(I, S, sh);
+      if (tid == 0) sh.safe = count_safe(S, sh);
+      __syncthreads();
+      if (sh.safe == 0) break;  // the pool held stale entries only
+    }
+    const int B = sh.safe < Bmax ? sh.safe : Bmax;
+    const int xb = sh.xb;
+    const double* xk = win_k(S, xb);
+    const uint32_t* xp = win_p(S, xb);
+    const uint32_t* xv = win_v(S, xb);
+    // ---- round trip 1: member versions and the members' neighbour slots
+    int pr_m[kPPT], pr_i[kPPT];
+    double pr_a[kPPT], pr_b[kPPT];
+#pragma unroll
+    for (int u = 0; u < kPPT; ++u) {
+      pr_m[u] = -1;
+      pr_i[u] = -1;
+      pr_a[u] = 0.0;
+      pr_b[u] = 0.0;
+      const int q = tid + u * NT;
+      if (q < B * PW) {
+        const int m = q / PW, k = q % PW;
+        const uint32_t j = xp[m] & 0x7fffffffu;
+        pr_m[u] = m;
+        if (k == D) {
+          pr_i[u] = (int)j;
+        } else {
+          const int64_t sl = slot_of(j, D, k);
+          pr_i[u] = I->col[sl];
+          pr_a[u] = I->A[sl];
+          pr_b[u] = I->Br[sl];
+        }
+      }
+    }
+    if (tid < B) S.mval[tid] = (I->ver[xp[tid] & 0x7fffffffu] == xv[tid]) ? 1 : 0;
+    for (int q = tid; q < kHash; q += NT) {
+      S.hidx[q] = 0u;
+      S.hown[q] = 0x7fffffff;
+    }
+    __syncthreads();
+    if (tid < 64) {  // ranks of the valid members, one wavefront
+      const bool v = tid < B && S.mval[tid] != 0;
+      const unsigned long long bal = __ballot(v);
+      const int r = __popcll(bal & ((1ull << tid) - 1ull));
+      if (tid < B) S.mrank[tid] = v ? r : -1;
+      if (v) {
+        S.mk[r] = xk[tid];
+        S.mp[r] = xp[tid];
+        S.mpos[r] = tid;
+      }
+      if (tid == 0) {
+        sh.nvalid = __popcll(bal);
+        sh.p = __popcll(bal);
+        sh.ns = 0;
+        sh.napp = 0;
+      }
+    }
+    __syncthreads();
+    const int nvalid = sh.nvalid;
+    int pr_r[kPPT];
+#pragma unroll
+    for (int u = 0; u < kPPT; ++u) {
+      pr_r[u] = (pr_m[u] >= 0) ? S.mrank[pr_m[u]] : -1;
+      if (pr_i[u] < 0) pr_r[u] = -1;  // padding slot
+    }
+    // ---- pairwise disjoint neighbour sets: lowest owning rank per magnet
+#pragma unroll
+    for (int u = 0; u < kPPT; ++u) {
+      if (pr_r[u] >= 0) {
+        const uint32_t want = (uint32_t)pr_i[u] + 1u;
+        uint32_t s = hash_slot((uint32_t)pr_i[u]);
+        while (true) {
+          const uint32_t old = atomicCAS(&S.hidx[s], 0u, want);
+          if (old == 0u || old == want) break;
+          s = (s + 1) & (kHash - 1);
+        }
+        atomicMin(&S.hown[s], pr_r[u]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPPT; ++u) {
+      if (pr_r[u] >= 0) {
+        const uint32_t want = (uint32_t)pr_i[u] + 1u;
+        uint32_t s = hash_slot((uint32_t)pr_i[u]);
+        while (S.hidx[s] != want) s = (s + 1) & (kHash - 1);
+        if (S.hown[s] < pr_r[u]) atomicMin(&sh.p, pr_r[u]);
+      }
+    }
+    __syncthreads();
+    const int p_ab = sh.p;
+    // ---- round trip 2: touched magnets of the conflict-free prefix
+    double nh_p[kPPT], nh_q[kPPT], nkey[kPPT], nd_p[kPPT], nd_q[kPPT];
+    uint32_t nver[kPPT];
+    int nsi[kPPT];
+#pragma unroll
+    for (int u = 0; u < kPPT; ++u) {
+      nkey[u] = 0.0;
+      const int k = (pr_m[u] >= 0) ? (tid + u * NT) % PW : D;
+      if (pr_r[u] >= 0 && pr_r[u] < p_ab && k < D) {
+        const int i = pr_i[u];
+        const uint32_t mpay = S.mp[pr_r[u]];
+        const double two = (mpay & 0x80000000u) ? 2.0 : -2.0;  // s_new = -s_old
+        const double da = two * pr_a[u], db = two * pr_b[u];
+        nh_p[u] = I->h_par[i] + da;
+        nh_q[u] = I->h_perp[i] + db;
+        if (mode == kFieldCarry) {
+          nd_p[u] = I->hd_par[i] + da;
+          nd_q[u] = I->hd_perp[i] + db;
+        }
+        nsi[u] = I->s[i];
+        nver[u] = I->ver[i];
+        nkey[u] = switching_key(nsi[u], nh_p[u], nh_q[u], I->hk[i], pb, pc, ep, eq);
+        if (nkey[u] > 0.0) {
+          // first later member of the prefix this magnet would beat
+          const uint32_t npay = (uint32_t)i | (nsi[u] < 0 ? 0x80000000u : 0u);
+          int lo = pr_r[u] + 1, hi = p_ab;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (better(nkey[u], npay, S.mk[mid], S.mp[mid])) hi = mid; else lo = mid + 1;
+          }
+          if (lo < p_ab) atomicMin(&sh.p, lo);
+        }
+      }
+    }
+    __syncthreads();
+    int p = sh.p;
+    if (p > max_flips - flips) p = (int)(max_flips - flips);
+    if (p <= 0 && nvalid > 0) {
+      status = -5;
+      break;
+    }
+    // ---- commit members [0, p) and their neighbours
+    if (tid < p) {
+      const uint32_t mpay = S.mp[tid];
+      const uint32_t j = mpay & 0x7fffffffu;
+      I->s[j] = (mpay & 0x80000000u) ? (int8_t)1 : (int8_t)-1;
+      I->key[j] = 0.0;
+      I->ver[j] = xv[S.mpos[tid]] + 1u;
+    }
+    if (tid == 0) {
+      for (int r = 0; r < p; ++r) {
+        const uint32_t j = S.mp[r] & 0x7fffffffu;
+        if (logpos < I->log_cap) {
+          I->log_t[logpos] = (int32_t)t;
+          I->log_j[logpos] = (int32_t)j;
+        }
+        ++logpos;
+        const uint64_t w = ((uint64_t)(uint32_t)t << 32) | (uint64_t)j;
+        hash = (hash ^ w) * 0x100000001b3ull;
+      }
+    }
+    const double cmk = sh.cmk;
+    const uint32_t cmp = sh.cmp, cmv = sh.cmv;
+    const int cb = sh.cb;
+    const int64_t ncold = sh.ncold;
+#pragma unroll
+    for (int u = 0; u < kPPT; ++u) {
+      const int k = (pr_m[u] >= 0) ? (tid + u * NT) % PW : D;
+      if (pr_r[u] >= 0 && pr_r[u] < p && k < D) {
+        const int i = pr_i[u];
+        I->h_par[i] = nh_p[u];
+        I->h_perp[i] = nh_q[u];
+        if (mode == kFieldCarry) {
+          I->hd_par[i] = nd_p[u];
+          I->hd_perp[i] = nd_q[u];
+        } else if (mode == kFieldDirty) {
+          I->dirty[i] = 1;
+        }
+        I->key[i] = nkey[u];
+        const uint32_t v1 = nver[u] + 1u;
+        I->ver[i] = v1;
+        if (nkey[u] > 0.0) {
+          const uint32_t npay = (uint32_t)i | (nsi[u] < 0 ? 0x80000000u : 0u);
+          if (better_e(nkey[u], npay, v1, cmk, cmp, cmv)) {
+            const int q = atomicAdd(&sh.ns, 1);
+            S.sk[q] = nkey[u];
+            S.sp[q] = npay;
+            S.sv[q] = v1;
+          } else {
+            const int64_t q = ncold + atomicAdd((unsigned long long*)&sh.napp, 1ull);
+            I->ckey[cb][q] = nkey[u];
+            I->cpay[cb][q] = npay;
+            I->cver[cb][q] = v1;
+          }
+        }
+      }
+    }
+    flips += p;
+    __syncthreads();
+    // window entries consumed: up to the last committed member (stale ones
+    // in between included), or the whole batch when every valid member went
+    const int consumed = (p < nvalid) ? S.mpos[p - 1] + 1 : B;
+    const int ns = sh.ns;
+    if (tid == 0) {
+      sh.ncold += sh.napp;
+      sh.ncold_out = sh.ncold;
+      sh.rk = sh.cmk;
+      sh.rp = sh.cmp;
+      sh.rv = sh.cmv;
+    }
+    __syncthreads();
+    sort_staging(S, ns);
+    const int na = sh.nx - consumed;
+    const int keep = na + ns < kWin ? na + ns : kWin;
+    merge_keep(I, S, sh, consumed, na, ns, keep, sh.cb);
+    if (tid == 0) {
+      sh.ncold = sh.ncold_out;
+      sh.cmk = sh.rk;
+      sh.cmp = sh.rp;
+      sh.cmv = sh.rv;
+    }
+    __syncthreads();
+  }
+  return status;
+}
+
 // Relax one instance at step t with the whole workgroup (Sec. II.H).  The
 // flippable keys are kept in a three-level max tree: the key array in
 // memory, first-level tiles of 2^l1_shift magnets and second-level groups of
 // 64 tiles in LDS, built from the per-64-row maxima of the field phase.
 // Per flip: the root gives j; thread 0 flips it and logs it; the threads
 // update j's neighbours (dipolar and total field += 2 s_new * coupling, new
-// key); the touched tiles and groups are rescanned.  Thread 0 then advances
-// the run cursor.  Returns the relax status (0 or ASI_ELOOP).
-__device__ int relax_step(const InstDev* __restrict__ I, RunDev* __restrict__ R, int64_t t,
-                          unsigned char* lds_raw, RelaxShared& sh) {
+// key); the touched tiles and groups are rescanned.  Returns 0 or -5 (flip
+// cap reached with a flippable magnet left).
+__device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t t, unsigned char* lds_raw,
+                          RelaxShared& sh, int64_t& flips, int64_t& logpos, uint64_t& hash) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int NT = blockDim.x, NW = NT >> 6;
   const int64_t n = I->n;
@@ -473,9 +1039,6 @@ __device__ int relax_step(const InstDev* __restrict__ I, RunDev* __restrict__ R,
   }
   __syncthreads();
 
-  int64_t flips = 0;
-  int64_t logpos = R->flips;
-  uint64_t hash = R->hash;
   int status = 0;
   const int per2 = (nt2 + 63) >> 6;
 
@@ -591,7 +1154,29 @@ __device__ int relax_step(const InstDev* __restrict__ I, RunDev* __restrict__ R,
     __syncthreads();
     if (tid == 0) sh.n2 = 0;
   }
-  if (tid == 0) {
+  return status;
+}
+
+// Relax one instance at step t (Sec. II.H) and advance its run cursor.
+// Steps that start with at least spec_min flippable magnets (and a degree
+// that leaves room for batches) take the speculative path; the others the
+// max tree.  Both flip exactly the magnets, in exactly the order, of the
+// one-at-a-time relax.
+__device__ __forceinline__ int relax_step(const InstDev* __restrict__ I, RunDev* __restrict__ R, int64_t t,
+                          unsigned char* lds_raw, RelaxShared& sh, SpecShared& ssh) {
+  const int64_t ncand = __hip_atomic_load(I->ccount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int64_t flips = 0;
+  int64_t logpos = R->flips;
+  uint64_t hash = R->hash;
+  int status;
+  if (blockDim.x == 1024 && I->D <= kSpecMaxD && ncand >= I->spec_min)
+    status = relax_spec(I, t, lds_raw + relax_tree_lds_bytes(I->n, I->l1_shift), ssh, ncand,
+                        flips, logpos, hash);
+  else
+    status = relax_tree(I, t, lds_raw, sh, flips, logpos, hash);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(I->ccount, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     R->flips += flips;
     R->flips_call += flips;
     R->hash = hash;
@@ -611,7 +1196,8 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
   if (!R->active) return;
   extern __shared__ unsigned char lds_raw[];
   __shared__ RelaxShared sh;
-  relax_step(insts + blockIdx.x, R, R->t, lds_raw, sh);
+  __shared__ SpecShared ssh;
+  relax_step(insts + blockIdx.x, R, R->t, lds_raw, sh, ssh);
 }
 
 // One workgroup per instance runs whole field steps -- its own field phase,
@@ -629,6 +1215,7 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_fused(const InstDev* __
   const InstDev* I = insts + blockIdx.x;
   extern __shared__ unsigned char lds_raw[];
   __shared__ RelaxShared sh;
+  __shared__ SpecShared ssh;
   __shared__ int go;
   const int wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
   const uint64_t t_start = wall_clock64();
@@ -641,7 +1228,7 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_fused(const InstDev* __
       __syncthreads();
     }
     ready = false;
-    if (relax_step(I, R, t, lds_raw, sh) != 0) break;
+    if (relax_step(I, R, t, lds_raw, sh, ssh) != 0) break;
     if (threadIdx.x == 0)
       go = (R->active && (budget_ticks <= 0 ||
                           (int64_t)(wall_clock64() - t_start) < budget_ticks)) ? 1 : 0;
@@ -726,18 +1313,18 @@ int32_t relax_l1_shift(int64_t n) {
 }
 
 size_t relax_lds_bytes(int64_t n, int32_t l1_shift) {
-  const int64_t nt1 = (n + (1LL << l1_shift) - 1) >> l1_shift;
-  const int64_t nt2 = (nt1 + kL2Group - 1) / kL2Group;
-  size_t off = 0;
-  off = align16(off + sizeof(double) * nt1);
-  off = align16(off + sizeof(uint32_t) * nt1);
-  off = align16(off + sizeof(int32_t) * nt1);
-  off = align16(off + sizeof(int32_t) * nt1);
-  off = align16(off + sizeof(double) * nt2);
-  off = align16(off + sizeof(uint32_t) * nt2);
-  off = align16(off + sizeof(int32_t) * nt2);
-  off = align16(off + sizeof(int32_t) * nt2);
-  return off;
+  return relax_tree_lds_bytes(n, l1_shift) + spec_lds_bytes();
+}
+
+hipError_t configure_kernels() {
+  // the relax kernels take more than 64 KB of dynamic LDS
+  const int bytes = (int)relax_lds_bytes((int64_t)kMaxL1Tiles << 6, 6);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_relax),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return e;
 }
 
 }  // namespace asi

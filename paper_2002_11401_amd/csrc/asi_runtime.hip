@@ -241,7 +241,7 @@ size_t footprint_estimate(int64_t n, int64_t D, int64_t K, int64_t log_cap) {
   const int64_t nsl = (n + kSlice - 1) / kSlice;
   size_t slots = (size_t)nsl * kSlice * (size_t)D;
   size_t b = slots * (4 + 8 + 8 + 8);
-  b += (size_t)n * (4 + 8 + 8 + 8 + 1 + 1 + 8 * 7);
+  b += (size_t)n * (4 + 8 + 8 + 8 + 1 + 1 + 8 * 7 + 4) + (size_t)(n + 8192) * 32;
   b += (size_t)nsl * 12 + (size_t)log_cap * 8 + (size_t)K * 20;
   b += 1 << 16;
   return b;
@@ -251,6 +251,11 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   asi_status st = validate(p);
   if (st != ASI_OK) return st;
   if (const char* f = std::getenv("ASI_FAIL_ALLOC")) s->mem.fail_next = (f[0] == '1');
+  {
+    static hipError_t cfg = configure_kernels();
+    if (cfg != hipSuccess)
+      return fail(ASI_EDEVICE, std::string("kernel configuration: ") + hipGetErrorString(cfg));
+  }
   if (dev) s->mem.dev = *dev;
   if (dev && dev->stream) {
     s->stream = (hipStream_t)dev->stream;
@@ -404,6 +409,21 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   I.log_cap = log_cap;
   I.step_flips = nullptr;
   I.max_flips = p->max_flips_per_step > 0 ? p->max_flips_per_step : 64 * n;
+  I.ccap = n + 8192;
+  I.ver = dalloc<uint32_t>(s, n);
+  for (int b = 0; b < 2; ++b) {
+    I.cpay[b] = dalloc<uint32_t>(s, I.ccap);
+    I.ckey[b] = dalloc<double>(s, I.ccap);
+    I.cver[b] = dalloc<uint32_t>(s, I.ccap);
+    if (!I.cpay[b] || !I.ckey[b] || !I.cver[b])
+      return fail(ASI_ENOMEM, "device allocation failed (candidate pool)");
+  }
+  I.ccount = dalloc<int32_t>(s, 1);
+  if (!I.ver || !I.ccount) return fail(ASI_ENOMEM, "device allocation failed (candidate pool)");
+  HIPCHK(hipMemsetAsync(I.ver, 0, 4 * n, s->stream), s);
+  HIPCHK(hipMemsetAsync(I.ccount, 0, 4, s->stream), s);
+  I.spec_min = 256;
+  if (const char* e = std::getenv("ASI_SPEC_MIN")) I.spec_min = std::atoll(e);
   s->dI = dalloc<InstDev>(s, 1);
   s->dR = dalloc<RunDev>(s, 1);
   s->nblocks = (n + kFieldBlock - 1) / kFieldBlock;
@@ -426,9 +446,9 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
          s);
   HIPCHK(hipMemcpyAsync(s->dI, &s->hI, sizeof(InstDev), hipMemcpyHostToDevice, s->stream), s);
   launch_set_run(s->dR, -1, -1, 0, 1, -1, s->stream);
-  // at least 4 wavefronts so the tiles touched by a flip are rescanned in
-  // parallel; one neighbour per lane where the degree allows
-  s->relax_waves = std::min(kMaxRelaxWaves, std::max(4, (D + 63) / 64));
+  // 16 wavefronts: the speculative relax spreads up to 2048 member and
+  // neighbour slots over 1024 lanes; touched tiles are rescanned in parallel
+  s->relax_waves = kMaxRelaxWaves;
   if (const char* w = std::getenv("ASI_RELAX_WAVES")) {
     int v = std::atoi(w);
     if (v >= 1 && v <= kMaxRelaxWaves) s->relax_waves = v;
