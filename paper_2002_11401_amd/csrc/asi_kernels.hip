@@ -332,44 +332,84 @@ __device__ __forceinline__ double field_row(const InstDev* __restrict__ I, int64
 
 // Field phase for the 64 rows starting at row0 (a multiple of 64), by one
 // wavefront: rows, then their maximum key into the per-64-row table.
-__device__ __forceinline__ void field_rows64(const InstDev* __restrict__ I, int64_t row0, int64_t t) {
+// Returns the lane's (key, payload) for the candidate pool.
+__device__ __forceinline__ double field_rows64(const InstDev* __restrict__ I, int64_t row0,
+                                               int64_t t, uint32_t& payload) {
   const int lane = threadIdx.x & 63;
   const int64_t i = row0 + lane;
   double key = 0.0;
-  uint32_t payload = 0;
+  payload = 0;
   if (i < I->n) key = field_row(I, i, t, payload);
-  // append the flippable rows to the candidate pool (one atomic per wave)
-  const unsigned long long bal = __ballot(key > 0.0);
-  if (bal) {
-    int base = 0;
-    if (lane == 0) base = atomicAdd(I->ccount, __popcll(bal));
-    base = __builtin_amdgcn_readfirstlane(base);
-    if (key > 0.0) {
-      const int64_t q = base + __popcll(bal & ((1ull << lane) - 1ull));
-      I->cpay[0][q] = payload;
-      I->ckey[0][q] = key;
-      I->cver[0][q] = I->ver[i];
-    }
-  }
-  wave_argmax(key, payload);
+  double mk = key;
+  uint32_t mp = payload;
+  wave_argmax(mk, mp);
   if (lane == 0) {
-    I->t1key[row0 >> 6] = key;
-    I->t1idx[row0 >> 6] = payload;
+    I->t1key[row0 >> 6] = mk;
+    I->t1idx[row0 >> 6] = mp;
+  }
+  return key;
+}
+
+// Append a flippable lane's entry at pool position base + its rank among
+// the flippable lanes of the wavefront.
+__device__ __forceinline__ void pool_put(const InstDev* __restrict__ I, double key,
+                                         uint32_t payload, unsigned long long bal, int64_t base) {
+  const int lane = threadIdx.x & 63;
+  if (key > 0.0) {
+    const int64_t q = base + __popcll(bal & ((1ull << lane) - 1ull));
+    const uint32_t i = payload & 0x7fffffffu;
+    I->cpay[0][q] = payload;
+    I->ckey[0][q] = key;
+    I->cver[0][q] = I->ver[i];
   }
 }
 
-// Grid-wide field pass: one lane per magnet, any number of instances.
+// Field phase by one wavefront, appending its flippable rows to the pool
+// with one atomic per wavefront.
+__device__ __forceinline__ void field_rows64_pool(const InstDev* __restrict__ I, int64_t row0,
+                                                  int64_t t) {
+  uint32_t payload;
+  const double key = field_rows64(I, row0, t, payload);
+  const unsigned long long bal = __ballot(key > 0.0);
+  if (bal) {
+    int base = 0;
+    if ((threadIdx.x & 63) == 0) base = atomicAdd(I->ccount, __popcll(bal));
+    base = __builtin_amdgcn_readfirstlane(base);
+    pool_put(I, key, payload, bal, base);
+  }
+}
+
+// Grid-wide field pass: one lane per magnet, any number of instances; the
+// block's flippable rows reach the pool with one atomic per block.
 __global__ __launch_bounds__(kFieldBlock) void k_field(const InstDev* __restrict__ insts,
                                                       RunDev* __restrict__ runs,
                                                       const int32_t* __restrict__ blk_inst,
                                                       const int32_t* __restrict__ blk_row0) {
+  __shared__ int wcount[kFieldBlock / 64];
+  __shared__ int bbase;
   const int q = blk_inst[blockIdx.x];
   const RunDev* R = runs + q;
   if (!R->active) return;
   const InstDev* I = insts + q;
-  const int64_t wave_row0 = (int64_t)blk_row0[blockIdx.x] + (threadIdx.x & ~63);
-  if (wave_row0 >= I->n) return;  // whole wavefront past the end
-  field_rows64(I, wave_row0, R->t);
+  const int wave = threadIdx.x >> 6;
+  const int64_t wave_row0 = (int64_t)blk_row0[blockIdx.x] + wave * 64;
+  uint32_t payload = 0;
+  double key = 0.0;
+  if (wave_row0 < I->n) key = field_rows64(I, wave_row0, R->t, payload);
+  const unsigned long long bal = __ballot(key > 0.0);
+  if ((threadIdx.x & 63) == 0) wcount[wave] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < kFieldBlock / 64; ++w) {
+      const int c = wcount[w];
+      wcount[w] = tot;
+      tot += c;
+    }
+    bbase = tot ? atomicAdd(I->ccount, tot) : 0;
+  }
+  __syncthreads();
+  if (bal) pool_put(I, key, payload, bal, (int64_t)bbase + wcount[wave]);
 }
 
 // ------------------------------------------------------------ relax
@@ -449,7 +489,7 @@ constexpr int kWin = 2048;        // hot window entries
 constexpr int kHash = 4096;       // conflict table slots
 constexpr int kMaxPairs = 2048;   // member + neighbour slots per batch
 constexpr int kMaxMembers = 64;
-constexpr int kSpecMaxD = 128;    // above this degree batches are too short to pay
+constexpr int kSpecMaxD = kMaxPairs - 1;  // at least one member per batch
 
 // Relax order of two magnets: larger key first, then lower index.
 __device__ inline bool better(double ka, uint32_t pa, double kb, uint32_t pb) {
@@ -638,17 +678,41 @@ __device__ __forceinline__ void merge_keep(const InstDev* I, const SpecLds& S, S
   __syncthreads();
 }
 
-// Sort staging entries [0, ns) best first (padded to a power of two).
+// Sort staging entries [0, ns) best first.  Up to one entry per thread:
+// each thread counts the entries that beat its own (every thread reads the
+// same entry at a time, a broadcast) and moves it to that rank; no two
+// entries tie under the pool order.  Larger sets: bitonic sort, padded to a
+// power of two.
 __device__ __forceinline__ void sort_staging(const SpecLds& S, int ns) {
+  const int tid = threadIdx.x;
+  if (ns <= (int)blockDim.x) {
+    double k = 0.0;
+    uint32_t p = 0, v = 0;
+    int rank = 0;
+    if (tid < ns) {
+      k = S.sk[tid];
+      p = S.sp[tid];
+      v = S.sv[tid];
+      for (int q = 0; q < ns; ++q) rank += better_e(S.sk[q], S.sp[q], S.sv[q], k, p, v) ? 1 : 0;
+    }
+    __syncthreads();
+    if (tid < ns) {
+      S.sk[rank] = k;
+      S.sp[rank] = p;
+      S.sv[rank] = v;
+    }
+    __syncthreads();
+    return;
+  }
   int P = 1;
   while (P < ns) P <<= 1;
-  for (int q = ns + threadIdx.x; q < P; q += blockDim.x) {
+  for (int q = ns + tid; q < P; q += blockDim.x) {
     S.sk[q] = -1.0;
     S.sp[q] = 0x7fffffffu;
     S.sv[q] = 0u;
   }
   __syncthreads();
-  if (P > 1) bitonic_best_first(S.sk, S.sp, S.sv, P);
+  bitonic_best_first(S.sk, S.sp, S.sv, P);
 }
 
 // Window := best kWin entries of (window + valid pool entries); the other
@@ -672,7 +736,7 @@ __device__ __forceinline__ void refill(const InstDev* I, const SpecLds& S, SpecS
       const bool ok = I->ver[pay & 0x7fffffffu] == ver;
       S.sk[q] = ok ? I->ckey[cb][c0 + q] : -1.0;
       S.sp[q] = ok ? pay : 0x7fffffffu;
-      S.sv[q] = ver;
+      S.sv[q] = ok ? ver : (uint32_t)q;  // invalid entries: distinct, sorted last
     }
     __syncthreads();
     sort_staging(S, m);
@@ -1224,7 +1288,7 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_fused(const InstDev* __
     const int64_t t = R->t;
     if (!ready) {
       for (int64_t row0 = (int64_t)wave * 64; row0 < I->n; row0 += (int64_t)NW * 64)
-        field_rows64(I, row0, t);
+        field_rows64_pool(I, row0, t);
       __syncthreads();
     }
     ready = false;

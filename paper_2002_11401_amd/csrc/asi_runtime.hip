@@ -377,6 +377,10 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   I.n = n;
   I.D = D;
   s->l1s = relax_l1_shift(n);
+  if (const char* e = std::getenv("ASI_L1_SHIFT")) {
+    const int v = std::atoi(e);
+    if (v > s->l1s && v <= 20) s->l1s = v;
+  }
   I.l1_shift = s->l1s;
   I.len = dlen;
   I.col = dcol;
