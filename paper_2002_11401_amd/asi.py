@@ -17,7 +17,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libasi.so")
+# ASI_LIBRARY may point at another build of the same library (kernel variants)
+LIB_PATH = os.environ.get("ASI_LIBRARY") or os.path.join(HERE, "libasi.so")
 
 ASI_OK, ASI_EINVAL, ASI_ENOMEM, ASI_EDEVICE, ASI_ESTATE, ASI_ELOOP, ASI_EBUSY = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "ASI_OK", -1: "ASI_EINVAL", -2: "ASI_ENOMEM", -3: "ASI_EDEVICE",

@@ -271,24 +271,26 @@ __device__ __forceinline__ double field_row(const InstDev* __restrict__ I, int64
     const double* __restrict__ B = I->B + base;
     // Chunks of 8 neighbours; the columns of the next chunk are fetched with
     // the couplings and spins of the current one, so each chunk costs one
-    // round trip.  Accumulation stays in ascending neighbour order.
+    // round trip.  Accumulation stays in ascending neighbour order.  The
+    // tables are streamed once per pass (non-temporal loads), which leaves
+    // the L2 to the gathered spins.
     p = 0.0;
     pq = 0.0;
     int32_t jc[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) jc[u] = (u < L) ? col[u * kSlice] : 0;
+    for (int u = 0; u < 8; ++u) jc[u] = (u < L) ? __builtin_nontemporal_load(&col[u * kSlice]) : 0;
     for (int32_t k = 0; k < L; k += 8) {
       double a[8], b[8];
       int sg[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const bool ok = k + u < L;
-        a[u] = ok ? A[(k + u) * kSlice] : 0.0;
-        b[u] = ok ? B[(k + u) * kSlice] : 0.0;
+        a[u] = ok ? __builtin_nontemporal_load(&A[(k + u) * kSlice]) : 0.0;
+        b[u] = ok ? __builtin_nontemporal_load(&B[(k + u) * kSlice]) : 0.0;
         sg[u] = ok ? s[jc[u]] : 0;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) jc[u] = (k + 8 + u < L) ? col[(k + 8 + u) * kSlice] : 0;
+      for (int u = 0; u < 8; ++u) jc[u] = (k + 8 + u < L) ? __builtin_nontemporal_load(&col[(k + 8 + u) * kSlice]) : 0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         if (k + u < L) {
@@ -489,7 +491,8 @@ constexpr int kWin = 2048;        // hot window entries
 constexpr int kHash = 4096;       // conflict table slots
 constexpr int kMaxPairs = 2048;   // member + neighbour slots per batch
 constexpr int kMaxMembers = 64;
-constexpr int kSpecMaxD = kMaxPairs - 1;  // at least one member per batch
+// Above this degree a batch holds too few members to beat the max tree.
+constexpr int kSpecMaxD = 128;
 
 // Relax order of two magnets: larger key first, then lower index.
 __device__ inline bool better(double ka, uint32_t pa, double kb, uint32_t pb) {

@@ -426,7 +426,7 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   if (!I.ver || !I.ccount) return fail(ASI_ENOMEM, "device allocation failed (candidate pool)");
   HIPCHK(hipMemsetAsync(I.ver, 0, 4 * n, s->stream), s);
   HIPCHK(hipMemsetAsync(I.ccount, 0, 4, s->stream), s);
-  I.spec_min = 256;
+  I.spec_min = 32;
   if (const char* e = std::getenv("ASI_SPEC_MIN")) I.spec_min = std::atoll(e);
   s->dI = dalloc<InstDev>(s, 1);
   s->dR = dalloc<RunDev>(s, 1);
