@@ -416,11 +416,15 @@ __global__ __launch_bounds__(kFieldBlock) void k_field(const InstDev* __restrict
 
 // ------------------------------------------------------------ relax
 struct RelaxLds {
-  double* l1k;
-  uint32_t* l1i;
-  int32_t* l1flag;
-  int32_t* l1list;
-  double* l2k;
+  double* l1k;                // first level: maximum key of each tile
+  uint32_t* l1i;              //   its index | sign bit
+  int32_t* l1flag;            //   tile touched by the current flip
+  int32_t* l1list;            //   touched tiles
+  unsigned long long* l1nk;   //   largest new key of the flip's updates (bits), 0: none
+  unsigned long long* l1ni;   //   lowest (index << 1 | spin<0) among updates with that key
+  int32_t* l1resc;            //   the tile's maximum was updated: rescan it
+  int32_t* l1rlist;           //   tiles to rescan
+  double* l2k;                // second level: maximum over 64 tiles
   uint32_t* l2i;
   int32_t* l2flag;
   int32_t* l2list;
@@ -432,10 +436,11 @@ __host__ __device__ inline size_t relax_tree_lds_bytes(int64_t n, int32_t l1_shi
   const int64_t nt1 = (n + (1LL << l1_shift) - 1) >> l1_shift;
   const int64_t nt2 = (nt1 + kL2Group - 1) / kL2Group;
   size_t off = 0;
+  off = align16(off + sizeof(unsigned long long) * nt1);
+  off = align16(off + sizeof(unsigned long long) * nt1);
   off = align16(off + sizeof(double) * nt1);
   off = align16(off + sizeof(uint32_t) * nt1);
-  off = align16(off + sizeof(int32_t) * nt1);
-  off = align16(off + sizeof(int32_t) * nt1);
+  for (int a = 0; a < 4; ++a) off = align16(off + sizeof(int32_t) * nt1);
   off = align16(off + sizeof(double) * nt2);
   off = align16(off + sizeof(uint32_t) * nt2);
   off = align16(off + sizeof(int32_t) * nt2);
@@ -446,6 +451,10 @@ __host__ __device__ inline size_t relax_tree_lds_bytes(int64_t n, int32_t l1_shi
 __device__ inline RelaxLds carve(unsigned char* base, int nt1, int nt2) {
   RelaxLds L;
   size_t off = 0;
+  L.l1nk = (unsigned long long*)(base + off);
+  off = align16(off + sizeof(unsigned long long) * nt1);
+  L.l1ni = (unsigned long long*)(base + off);
+  off = align16(off + sizeof(unsigned long long) * nt1);
   L.l1k = (double*)(base + off);
   off = align16(off + sizeof(double) * nt1);
   L.l1i = (uint32_t*)(base + off);
@@ -453,6 +462,10 @@ __device__ inline RelaxLds carve(unsigned char* base, int nt1, int nt2) {
   L.l1flag = (int32_t*)(base + off);
   off = align16(off + sizeof(int32_t) * nt1);
   L.l1list = (int32_t*)(base + off);
+  off = align16(off + sizeof(int32_t) * nt1);
+  L.l1resc = (int32_t*)(base + off);
+  off = align16(off + sizeof(int32_t) * nt1);
+  L.l1rlist = (int32_t*)(base + off);
   off = align16(off + sizeof(int32_t) * nt1);
   L.l2k = (double*)(base + off);
   off = align16(off + sizeof(double) * nt2);
@@ -465,7 +478,7 @@ __device__ inline RelaxLds carve(unsigned char* base, int nt1, int nt2) {
 }
 
 struct RelaxShared {
-  int n1, n2;
+  int n1, n2, nr;
   double key;
   uint32_t pay;
 };
@@ -1087,10 +1100,14 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
     L.l1k[e] = bk;
     L.l1i[e] = bi;
     L.l1flag[e] = 0;
+    L.l1nk[e] = 0ull;
+    L.l1ni[e] = ~0ull;
+    L.l1resc[e] = 0;
   }
   if (tid == 0) {
     sh.n1 = 0;
     sh.n2 = 0;
+    sh.nr = 0;
   }
   __syncthreads();
   for (int g = wave; g < nt2; g += NW) {
@@ -1149,12 +1166,23 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
       const uint64_t w = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)j;
       hash = (hash ^ w) * 0x100000001b3ull;
       const int e = (int)(j >> l1s);
+      L.l1resc[e] = 1;  // j was its tile's maximum
       if (atomicExch(&L.l1flag[e], 1) == 0) L.l1list[atomicAdd(&sh.n1, 1)] = e;
     }
     ++logpos;
     ++flips;
     const double two = (s_new > 0) ? 2.0 : -2.0;
-    for (int k = tid; k < D; k += NT) {
+    // Update the neighbours.  A touched tile whose maximum was not among the
+    // updated magnets keeps that maximum unless an update beats it, so it
+    // needs no rescan: the largest new key of the tile is found with LDS
+    // atomics (positive doubles order like their bit patterns), then the
+    // lowest index among the updates holding it.
+    const bool incr = D <= 2 * NT;
+    int u_i[2], u_e[2], u_s[2];
+    double u_k[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) u_i[h] = -1;
+    for (int k = tid, h = 0; k < D; k += NT, ++h) {
       const int64_t sl = slot_of(j, D, k);
       const int32_t i = colp[sl];
       if (i >= 0) {
@@ -1174,12 +1202,54 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
         keyp[i] = kk;
         const int e = (int)(i >> l1s);
         if (atomicExch(&L.l1flag[e], 1) == 0) L.l1list[atomicAdd(&sh.n1, 1)] = e;
+        if (!incr || (L.l1k[e] > 0.0 && (L.l1i[e] & 0x7fffffffu) == (uint32_t)i))
+          L.l1resc[e] = 1;
+        if (kk > 0.0) atomicMax(&L.l1nk[e], (unsigned long long)__double_as_longlong(kk));
+        if (h < 2) {
+          u_i[h] = i;
+          u_e[h] = e;
+          u_s[h] = si;
+          u_k[h] = kk;
+        }
+      }
+    }
+    __syncthreads();
+    if (incr) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (u_i[h] >= 0 && u_k[h] > 0.0 &&
+            (unsigned long long)__double_as_longlong(u_k[h]) == L.l1nk[u_e[h]])
+          atomicMin(&L.l1ni[u_e[h]], ((unsigned long long)u_i[h] << 1) | (u_s[h] < 0 ? 1ull : 0ull));
       }
     }
     __syncthreads();
     const int n1 = sh.n1;
-    for (int u = wave; u < n1; u += NW) {
+    for (int u = tid; u < n1; u += NT) {
       const int e = L.l1list[u];
+      if (L.l1resc[e]) {
+        L.l1rlist[atomicAdd(&sh.nr, 1)] = e;
+      } else {
+        const unsigned long long nkb = L.l1nk[e];
+        if (nkb != 0ull) {
+          const double nk = __longlong_as_double((long long)nkb);
+          const unsigned long long ni = L.l1ni[e];
+          const uint32_t np = (uint32_t)(ni >> 1) | ((ni & 1ull) ? 0x80000000u : 0u);
+          if (!(L.l1k[e] > 0.0) || better(nk, np, L.l1k[e], L.l1i[e])) {
+            L.l1k[e] = nk;
+            L.l1i[e] = np;
+          }
+        }
+        L.l1flag[e] = 0;
+        const int g = e / kL2Group;
+        if (atomicExch(&L.l2flag[g], 1) == 0) L.l2list[atomicAdd(&sh.n2, 1)] = g;
+      }
+      L.l1nk[e] = 0ull;
+      L.l1ni[e] = ~0ull;
+    }
+    __syncthreads();
+    const int nr = sh.nr;
+    for (int u = wave; u < nr; u += NW) {
+      const int e = L.l1rlist[u];
       const int64_t r0 = ((int64_t)e << l1s) + (int64_t)lane * seg;
       double bk = 0.0;
       uint32_t bp = 0;
@@ -1199,12 +1269,16 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
         L.l1k[e] = bk;
         L.l1i[e] = bp;
         L.l1flag[e] = 0;
+        L.l1resc[e] = 0;
         const int g = e / kL2Group;
         if (atomicExch(&L.l2flag[g], 1) == 0) L.l2list[atomicAdd(&sh.n2, 1)] = g;
       }
     }
     __syncthreads();
-    if (tid == 0) sh.n1 = 0;
+    if (tid == 0) {
+      sh.n1 = 0;
+      sh.nr = 0;
+    }
     const int n2 = sh.n2;
     for (int u = wave; u < n2; u += NW) {
       const int g = L.l2list[u];
@@ -1237,8 +1311,7 @@ __device__ __forceinline__ int relax_step(const InstDev* __restrict__ I, RunDev*
   uint64_t hash = R->hash;
   int status;
   if (blockDim.x == 1024 && I->D <= kSpecMaxD && ncand >= I->spec_min)
-    status = relax_spec(I, t, lds_raw + relax_tree_lds_bytes(I->n, I->l1_shift), ssh, ncand,
-                        flips, logpos, hash);
+    status = relax_spec(I, t, lds_raw, ssh, ncand, flips, logpos, hash);
   else
     status = relax_tree(I, t, lds_raw, sh, flips, logpos, hash);
   __syncthreads();
@@ -1380,7 +1453,9 @@ int32_t relax_l1_shift(int64_t n) {
 }
 
 size_t relax_lds_bytes(int64_t n, int32_t l1_shift) {
-  return relax_tree_lds_bytes(n, l1_shift) + spec_lds_bytes();
+  // one relax path runs per step, so the two share the space
+  const size_t a = relax_tree_lds_bytes(n, l1_shift), b = spec_lds_bytes();
+  return a > b ? a : b;
 }
 
 hipError_t configure_kernels() {
