@@ -14,6 +14,7 @@ E (directed neighbour pairs) x steps / wall time, with the relax included.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,6 +31,35 @@ HBM_PEAK_GBS = 8000.0
 def progress(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 METRIC = "neighbour interactions/s & flips/s; batched/served runs/s + p99 vs plain"
+
+
+PROFILE = os.path.join(ROOT, "profiles", "k_field_kagome577_rotating.md")
+
+
+def field_pass_digest():
+    """SHA-256 of the kernel source the full-field pass is built from."""
+    txt = open(os.path.join(ROOT, "paper_2002_11401_amd", "csrc", "asi_kernels.hip")).read()
+    a = txt.index("// ------------------------------------------------------------ neighbours")
+    b = txt.index("// ------------------------------------------------------------ field phase")
+    c = txt.index("// ------------------------------------------------------------ relax")
+    return hashlib.sha256((txt[:a] + txt[b:c]).encode()).hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per full-field pass from the committed counter summary, if it
+    was taken with the current kernel source; else None."""
+    try:
+        rec = {}
+        for line in open(PROFILE):
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch",
+                                                      "field_pass_source_sha256"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+        if rec.get("field_pass_source_sha256") == field_pass_digest():
+            return float(rec["traffic_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
 
 
 def cpu_baseline(w, target_s: float = 15.0):
@@ -103,7 +133,8 @@ def bench_plain(args, asi, workloads, torch):
                   "ns_per_flip": tm["relax_ms"] * 1e6 / max(1, flips),
                   "flips_per_s_in_kernel": flips / max(1e-9, tm["relax_ms"] / 1e3)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic() if w.name == "kagome577_rotating" else None,
                      "kernel": "k_field (full-field pass)"},
         "paper_context": {"field_calcs_per_s": 1e8, "hardware": "NVIDIA Tesla V100 32GB",
                           "workload": "square ASI, 8-spin neighbourhood, saturated size"},
@@ -164,6 +195,8 @@ def bench_served(args, asi, workloads, torch):
     bitwise against its served result)."""
     jobs = workloads.served_stream(count=args.jobs, seed=5, rate_per_s=args.rate,
                                    n_range=(1e3, args.max_n))
+    progress(f"generating {len(jobs)} job inputs")
+    wls = {j.job: j.workload() for j in jobs}
     srv = asi.Server(hbm_budget_bytes=int(args.budget_gb * (1 << 30)), max_slots=args.slots)
     ids = {}
     open_ids = {}
@@ -180,7 +213,7 @@ def bench_served(args, asi, workloads, torch):
         now = time.perf_counter() - t0
         while pending and pending[0].arrival_s <= now:
             j = pending.pop(0)
-            ids[j.job] = open_ids[j.job] = srv.submit(j.workload())
+            ids[j.job] = open_ids[j.job] = srv.submit(wls[j.job])
         active = srv.step(args.burst_ms)
         for job, jid in list(open_ids.items()):
             if srv.poll(jid):
@@ -201,7 +234,7 @@ def bench_served(args, asi, workloads, torch):
     t1 = time.perf_counter()
     for c, q in enumerate(sample):
         j = jobs[q]
-        w = j.workload()
+        w = wls[j.job]
         torch.cuda.synchronize()
         ts = time.perf_counter()
         s = asi.Sim.from_workload(w, device="hip")
