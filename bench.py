@@ -223,6 +223,7 @@ def bench_served(args, asi, workloads, torch):
             time.sleep(max(0.0, pending[0].arrival_s - (time.perf_counter() - t0)))
     t_all = time.perf_counter() - t0
     res = {job: srv.take(jid) for job, jid in ids.items()}
+    stats = srv.stats()
     srv.close()
     lats = np.array([lat[j.job] - j.arrival_s for j in jobs])
     # plain rate from a seeded uniform sample, each job alone
@@ -264,7 +265,8 @@ def bench_served(args, asi, workloads, torch):
             "speedup_vs_plain": (len(jobs) / t_all) * mean_plain,
             "latency_s": {"p50": float(np.percentile(lats, 50)),
                           "p99": float(np.percentile(lats, 99)), "max": float(lats.max())},
-            "bitwise_identical_to_plain": bool(same), "bitwise_checked_jobs": k}
+            "bitwise_identical_to_plain": bool(same), "bitwise_checked_jobs": k,
+            "server_stats": stats}
 
 
 def main():

@@ -195,10 +195,14 @@ asi_status asi_server_create(const asi_device* dev, size_t hbm_budget_bytes,
  * budget. */
 asi_status asi_server_submit(asi_server_t s, const asi_params* p, int64_t n_steps,
                              const double* h_xy, int64_t* job_id_out);
-/* Advance the server: admit what fits (neighbour tables built at
- * admission), run every resident job for up to about budget_ms of device time
- * (each job's workgroup advancing through its own protocol), retire finished
- * ones.  active_out (may be NULL): jobs still queued or resident. */
+/* Advance the server by one burst: run every resident job for about
+ * budget_ms of device time (each job's workgroup advancing through its own
+ * protocol; a relax still running at the deadline pauses mid-step and
+ * resumes in the next burst), admit queued jobs that fit while the burst
+ * runs (neighbour tables built at admission; they join the next burst), then
+ * retire finished ones.  With few resident jobs, at least one of them large,
+ * a burst is one field step of every job, with the field pass spread over the
+ * whole device.  active_out (may be NULL): jobs still queued or resident. */
 asi_status asi_server_step(asi_server_t s, double budget_ms, int32_t* active_out);
 /* done_out = 1 when the job has finished (non-blocking). */
 asi_status asi_server_poll(asi_server_t s, int64_t job_id, int32_t* done_out);
@@ -207,6 +211,19 @@ asi_status asi_server_poll(asi_server_t s, int64_t job_id, int32_t* done_out);
  * finished.  The job's memory is released on take. */
 asi_status asi_server_take(asi_server_t s, int64_t job_id, int8_t* spins, int64_t* flips,
                            uint64_t* flip_hash, double* t_admit, double* t_done);
+/* Counters since the server was created.  Host seconds are wall time of
+ * the calling thread; admit_s overlaps device bursts. */
+typedef struct {
+  int64_t bursts;    /* device bursts launched                                 */
+  int64_t admitted;  /* jobs created on the device                             */
+  int64_t retired;   /* jobs that finished on the device (done or ELOOP)       */
+  int64_t pauses;    /* relaxes stopped at a burst deadline, resumed later      */
+  double admit_s;    /* creating admitted jobs                                 */
+  double wait_s;     /* waiting for bursts after admission                     */
+  double retire_s;   /* reading results back and releasing jobs                */
+  double rebuild_s;  /* rebuilding the launch tables after admissions/retires  */
+} asi_server_stats;
+asi_status asi_server_get_stats(asi_server_t s, asi_server_stats* out);
 asi_status asi_server_destroy(asi_server_t s);
 
 #ifdef __cplusplus

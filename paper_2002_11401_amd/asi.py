@@ -67,6 +67,12 @@ class AsiTiming(C.Structure):
                 ("relax_launches", C.c_int64), ("relax_ms", C.c_double)]
 
 
+class AsiServerStats(C.Structure):
+    _fields_ = [("bursts", C.c_int64), ("admitted", C.c_int64), ("retired", C.c_int64),
+                ("pauses", C.c_int64), ("admit_s", C.c_double), ("wait_s", C.c_double),
+                ("retire_s", C.c_double), ("rebuild_s", C.c_double)]
+
+
 # Every entry point of include/asi.h with its ctypes signature.
 P = C.c_void_p
 I64P = C.POINTER(C.c_int64)
@@ -92,6 +98,7 @@ SIGNATURES = {
     "asi_server_poll": [P, C.c_int64, C.POINTER(C.c_int32)],
     "asi_server_take": [P, C.c_int64, P, I64P, C.POINTER(C.c_uint64),
                         C.POINTER(C.c_double), C.POINTER(C.c_double)],
+    "asi_server_get_stats": [P, C.POINTER(AsiServerStats)],
     "asi_server_destroy": [P],
 }
 
@@ -371,3 +378,8 @@ class Server:
         _check(library().asi_server_take(self._h, int(jid), _ptr(s), C.byref(f), C.byref(h),
                                          C.byref(ta), C.byref(td)))
         return dict(spins=s, flips=f.value, hash=h.value, t_admit=ta.value, t_done=td.value)
+
+    def stats(self) -> dict:
+        st = AsiServerStats()
+        _check(library().asi_server_get_stats(self._h, C.byref(st)))
+        return {name: getattr(st, name) for name, _ in AsiServerStats._fields_}

@@ -87,6 +87,13 @@ struct RunDev {
   int64_t flips_call; // flips since the host last cleared it
   uint64_t hash;      // running flip-log hash
   int64_t cur_step;   // last relaxed step
+  // A relax stopped at a deadline part-way through step t leaves active = 0
+  // and paused = 1; its next fused launch rebuilds the relax structures from
+  // the key array and continues step t.  step_acc counts the flips step t
+  // has made so far.
+  int32_t paused;
+  int32_t pad0;
+  int64_t step_acc;
 };
 
 void launch_neighbour_count(const double* x, const double* y, const int32_t* cellx,
@@ -105,9 +112,10 @@ void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,
 void launch_relax(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
                   size_t lds_bytes, hipStream_t st);
 // One workgroup per instance: up to max_steps whole steps (field phase and
-// relax) per instance, stopping early once budget_ticks of the device's
-// constant-rate clock have passed (0: no budget).  With first_ready the
-// fields of each instance's first step were already computed.
+// relax) per instance.  With budget_ticks > 0 a workgroup stops once that
+// many ticks of the device's constant-rate clock have passed: between steps,
+// or inside a relax (which then pauses, see RunDev).  With first_ready the
+// fields of each active instance's first step were already computed.
 void launch_fused(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
                   size_t lds_bytes, int64_t max_steps, int64_t budget_ticks,
                   int32_t first_ready, hipStream_t st);

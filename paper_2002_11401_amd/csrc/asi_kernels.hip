@@ -479,9 +479,15 @@ __device__ inline RelaxLds carve(unsigned char* base, int nt1, int nt2) {
 
 struct RelaxShared {
   int n1, n2, nr;
+  int pause;  // the relax stops here and resumes in a later launch
   double key;
   uint32_t pay;
 };
+
+// True once the deadline (device constant-rate clock; 0: none) has passed.
+__device__ inline bool past(uint64_t deadline) {
+  return deadline != 0 && wall_clock64() > deadline;
+}
 
 // ------------------------------------------------------------ speculative relax
 // Exact-order batched relax for steps that start with many flippable
@@ -575,7 +581,7 @@ __device__ inline SpecLds carve_spec(unsigned char* base) {
 }
 
 struct SpecShared {
-  int nx, xb, ns, nvalid, p, safe, cb;
+  int nx, xb, ns, nvalid, p, safe, cb, pause;
   int64_t ncold, ncold_out, napp;
   double cmk;       // cold_max (key, payload, version); key -1: pool empty
   uint32_t cmp, cmv;
@@ -799,10 +805,11 @@ __device__ inline uint32_t hash_slot(uint32_t i) { return (i * 2654435761u) >> (
 
 // Relax at step t in speculative batches (needs 1024 threads).  flips,
 // logpos and hash are the running counters (logpos and hash significant in
-// thread 0).  Returns 0 or -5 (flip cap reached with a flippable magnet left).
+// thread 0).  Returns 0, -5 (flip cap reached with a flippable magnet left)
+// or 1 (deadline passed after at least one batch, flippable magnets left).
 __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t t, unsigned char* lds,
                           SpecShared& sh, int64_t ncand, int64_t& flips, int64_t& logpos,
-                          uint64_t& hash) {
+                          uint64_t& hash, uint64_t deadline) {
   constexpr int kPPT = kMaxPairs / 1024;  // pair slots per thread
   const int tid = threadIdx.x, NT = blockDim.x;
   SpecLds S = carve_spec(lds);
@@ -824,15 +831,24 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
   }
   __syncthreads();
   int status = 0;
+  const int64_t flips0 = flips;
   while (true) {
-    if (tid == 0) sh.safe = count_safe(S, sh);
+    if (tid == 0) {
+      sh.safe = count_safe(S, sh);
+      sh.pause = (flips > flips0 && past(deadline)) ? 1 : 0;
+    }
     __syncthreads();
+    const int pause = sh.pause;
     if (sh.safe == 0 || sh.ncold + kMaxPairs + kWin > I->ccap) {
       if (sh.ncold == 0 && sh.safe == 0) break;
       refill(I, S, sh);
       if (tid == 0) sh.safe = count_safe(S, sh);
       __syncthreads();
       if (sh.safe == 0) break;  // the pool held stale entries only
+    }
+    if (pause) {  // flippable magnets remain
+      status = 1;
+      break;
     }
     const int B = sh.safe < Bmax ? sh.safe : Bmax;
     const int xb = sh.xb;
@@ -1052,10 +1068,12 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
 // 64 tiles in LDS, built from the per-64-row maxima of the field phase.
 // Per flip: the root gives j; thread 0 flips it and logs it; the threads
 // update j's neighbours (dipolar and total field += 2 s_new * coupling, new
-// key); the touched tiles and groups are rescanned.  Returns 0 or -5 (flip
-// cap reached with a flippable magnet left).
+// key); the touched tiles and groups are rescanned.  Returns 0, -5 (flip
+// cap reached with a flippable magnet left) or 1 (deadline passed, checked
+// every 16 flips, with flippable magnets left).
 __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t t, unsigned char* lds_raw,
-                          RelaxShared& sh, int64_t& flips, int64_t& logpos, uint64_t& hash) {
+                          RelaxShared& sh, int64_t& flips, int64_t& logpos, uint64_t& hash,
+                          uint64_t deadline) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int NT = blockDim.x, NW = NT >> 6;
   const int64_t n = I->n;
@@ -1125,6 +1143,7 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
 
   int status = 0;
   const int per2 = (nt2 + 63) >> 6;
+  const int64_t flips0 = flips;
 
   while (true) {
     if (wave == 0) {
@@ -1144,12 +1163,17 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
       if (lane == 0) {
         sh.key = bk;
         sh.pay = bp;
+        sh.pause = (flips > flips0 && ((flips - flips0) & 15) == 0 && past(deadline)) ? 1 : 0;
       }
     }
     __syncthreads();
     const double top = sh.key;
     const uint32_t pay = sh.pay;
     if (!(top > 0.0)) break;
+    if (sh.pause) {
+      status = 1;
+      break;
+    }
     if (flips >= max_flips) {
       status = -5;
       break;
@@ -1304,30 +1328,68 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
 // max tree.  Both flip exactly the magnets, in exactly the order, of the
 // one-at-a-time relax.
 __device__ __forceinline__ int relax_step(const InstDev* __restrict__ I, RunDev* __restrict__ R, int64_t t,
-                          unsigned char* lds_raw, RelaxShared& sh, SpecShared& ssh) {
+                          unsigned char* lds_raw, RelaxShared& sh, SpecShared& ssh,
+                          uint64_t deadline) {
   const int64_t ncand = __hip_atomic_load(I->ccount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  int64_t flips = 0;
+  const int64_t acc0 = R->step_acc;  // flips of step t before a pause
+  int64_t flips = acc0;
   int64_t logpos = R->flips;
   uint64_t hash = R->hash;
   int status;
   if (blockDim.x == 1024 && I->D <= kSpecMaxD && ncand >= I->spec_min)
-    status = relax_spec(I, t, lds_raw, ssh, ncand, flips, logpos, hash);
+    status = relax_spec(I, t, lds_raw, ssh, ncand, flips, logpos, hash, deadline);
   else
-    status = relax_tree(I, t, lds_raw, sh, flips, logpos, hash);
+    status = relax_tree(I, t, lds_raw, sh, flips, logpos, hash, deadline);
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_store(I->ccount, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    R->flips += flips;
-    R->flips_call += flips;
+    R->flips += flips - acc0;
+    R->flips_call += flips - acc0;
     R->hash = hash;
-    if (t >= 0 && t < I->K && I->step_flips) I->step_flips[t] = (int32_t)flips;
-    R->cur_step = t;
-    R->t = t + 1;
-    if (status != 0) R->status = status;
-    R->active = (status == 0 && R->t < R->t_end) ? 1 : 0;
+    if (status == 1) {
+      R->step_acc = flips;
+      R->paused = 1;
+      R->active = 0;
+    } else {
+      if (t >= 0 && t < I->K && I->step_flips) I->step_flips[t] = (int32_t)flips;
+      R->step_acc = 0;
+      R->paused = 0;
+      R->cur_step = t;
+      R->t = t + 1;
+      if (status != 0) R->status = status;
+      R->active = (status == 0 && R->t < R->t_end) ? 1 : 0;
+    }
   }
   __syncthreads();
   return status;
+}
+
+// Relax structures of a paused instance, rebuilt from its state: the
+// per-64-row maxima of the exact keys and a fresh candidate pool (entries
+// carry the current versions), as its field phase would have left them.
+__device__ __forceinline__ void resume_rows64(const InstDev* __restrict__ I, int64_t row0) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = row0 + lane;
+  double key = 0.0;
+  uint32_t payload = 0;
+  if (i < I->n) {
+    key = I->key[i];
+    payload = (uint32_t)i | (I->s[i] < 0 ? 0x80000000u : 0u);
+  }
+  double mk = key;
+  uint32_t mp = payload;
+  wave_argmax(mk, mp);
+  if (lane == 0) {
+    I->t1key[row0 >> 6] = mk;
+    I->t1idx[row0 >> 6] = mp;
+  }
+  const unsigned long long bal = __ballot(key > 0.0);
+  if (bal) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(I->ccount, __popcll(bal));
+    base = __builtin_amdgcn_readfirstlane(base);
+    pool_put(I, key, payload, bal, base);
+  }
 }
 
 __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __restrict__ insts,
@@ -1337,21 +1399,25 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
   extern __shared__ unsigned char lds_raw[];
   __shared__ RelaxShared sh;
   __shared__ SpecShared ssh;
-  relax_step(insts + blockIdx.x, R, R->t, lds_raw, sh, ssh);
+  relax_step(insts + blockIdx.x, R, R->t, lds_raw, sh, ssh, 0);
 }
 
 // One workgroup per instance runs whole field steps -- its own field phase,
 // wavefront by wavefront, then the relax -- through its own protocol, so
 // instances never wait for each other between steps.  Stops after max_steps
 // steps, at the end of the protocol, on ELOOP, or once budget_ticks of the
-// constant-rate device clock have passed (checked between steps).
+// constant-rate device clock have passed: checked between steps and inside
+// the relax, which then pauses mid-step.  A paused instance first rebuilds
+// its relax structures and finishes the step it stopped in; the flips it
+// makes, and their order, are those of an uninterrupted relax.
 __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_fused(const InstDev* __restrict__ insts,
                                                               RunDev* __restrict__ runs,
                                                               int64_t max_steps,
                                                               int64_t budget_ticks,
                                                               int32_t first_ready) {
   RunDev* R = runs + blockIdx.x;
-  if (!R->active) return;
+  const bool paused = R->paused != 0;
+  if (!R->active && !paused) return;
   const InstDev* I = insts + blockIdx.x;
   extern __shared__ unsigned char lds_raw[];
   __shared__ RelaxShared sh;
@@ -1359,7 +1425,14 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_fused(const InstDev* __
   __shared__ int go;
   const int wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
   const uint64_t t_start = wall_clock64();
+  const uint64_t deadline = budget_ticks > 0 ? t_start + (uint64_t)budget_ticks : 0;
   bool ready = first_ready != 0;
+  if (paused) {
+    for (int64_t row0 = (int64_t)wave * 64; row0 < I->n; row0 += (int64_t)NW * 64)
+      resume_rows64(I, row0);
+    __syncthreads();
+    ready = true;
+  }
   for (int64_t k = 0; k < max_steps; ++k) {
     const int64_t t = R->t;
     if (!ready) {
@@ -1368,10 +1441,8 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_fused(const InstDev* __
       __syncthreads();
     }
     ready = false;
-    if (relax_step(I, R, t, lds_raw, sh, ssh) != 0) break;
-    if (threadIdx.x == 0)
-      go = (R->active && (budget_ticks <= 0 ||
-                          (int64_t)(wall_clock64() - t_start) < budget_ticks)) ? 1 : 0;
+    if (relax_step(I, R, t, lds_raw, sh, ssh, deadline) != 0) break;
+    if (threadIdx.x == 0) go = (R->active && !past(deadline)) ? 1 : 0;
     __syncthreads();
     if (!go) break;
   }
@@ -1387,6 +1458,8 @@ __global__ void k_set_run(RunDev* R, int64_t t, int64_t t_end, int32_t active,
   R->active = active;
   R->status = 0;
   R->flips_call = 0;
+  R->paused = 0;
+  R->step_acc = 0;
   if (reset_log) {
     R->flips = 0;
     R->hash = 0xcbf29ce484222325ull;

@@ -865,6 +865,7 @@ struct Job {
   asi_sim* h = nullptr;  // while resident
   int32_t slot = -1;
   int state = 0;         // 0 queued, 1 resident, 2 done, 3 failed
+  int32_t passed = 0;    // later jobs admitted while this one waited at the head
   asi_status err = ASI_OK;
   std::vector<int8_t> spins_out;
   int64_t flips = 0;
@@ -910,8 +911,9 @@ int64_t degree_bound(const asi_params* p) {
 }  // namespace
 
 struct asi_server {
-  asi_device dev{};
-  hipStream_t stream = nullptr;
+  asi_device dev{};   // bursts run on dev.stream
+  asi_device cdev{};  // admission (job creation) runs on cdev.stream
+  hipStream_t stream = nullptr, cstream = nullptr;
   size_t budget = 0, used = 0;
   int32_t max_slots = 0;
   int64_t next_id = 0;
@@ -920,11 +922,21 @@ struct asi_server {
   std::vector<int64_t> slots;  // job id per slot, -1 free
   Table T;
   bool dirty = true;
-  std::vector<RunDev> runs;
+  std::vector<RunDev> runs;     // host copy of every slot's run cursor
+  RunDev* rb = nullptr;         // pinned read-back of the burst's cursors
+  std::vector<char> in_burst;   // slot took part in the running burst
   int64_t clock_hz = 100000000;  // device constant-rate clock
+  asi_server_stats stats{};
 };
 
 namespace {
+
+// A burst runs one field step per job (grid-wide field pass, then the
+// relaxes) instead of per-workgroup protocols when at most this many jobs are
+// resident and one of them has at least kTailMagnets magnets: a lone large
+// job's field phase would otherwise stream through a single compute unit.
+constexpr int32_t kTailJobs = 8;
+constexpr int64_t kTailMagnets = 1 << 16;
 
 asi_status server_rebuild(asi_server* S) {
   std::vector<InstDev> insts(S->max_slots);
@@ -950,6 +962,60 @@ asi_status server_rebuild(asi_server* S) {
   return ASI_OK;
 }
 
+// Admit queued jobs in arrival order while a slot is free.  A job whose
+// footprint does not fit the remaining budget is passed by later jobs that
+// fit, until max_slots jobs have passed it at the head of the queue; then
+// admission waits for memory to free up for it.  Creation runs on the
+// admission stream, alongside a running burst.
+asi_status server_admit(asi_server* S) {
+  size_t qi = 0;
+  int32_t slot = 0;
+  while (qi < S->queue.size()) {
+    while (slot < S->max_slots && S->slots[slot] >= 0) ++slot;
+    if (slot >= S->max_slots) break;
+    Job& J = *S->jobs[S->queue[qi]];
+    if (S->used + J.foot > S->budget) {
+      if (qi == 0 && J.passed >= S->max_slots) break;
+      ++qi;
+      continue;
+    }
+    S->queue.erase(S->queue.begin() + (std::ptrdiff_t)qi);
+    if (qi > 0) S->jobs[S->queue.front()]->passed++;
+    asi_params p = J.p;
+    p.xy = J.xy.data();
+    p.theta = J.theta.data();
+    p.hk = J.hk.data();
+    p.spin0 = J.spin0.empty() ? nullptr : J.spin0.data();
+    asi_handle h = nullptr;
+    asi_status st = asi_create(&p, &S->cdev, &h);
+    if (st == ASI_OK) st = asi_set_field_protocol(h, J.K, J.H.data());
+    if (st != ASI_OK) {
+      if (h) asi_destroy(h);
+      J.state = 3;
+      J.err = st;
+      J.t_done = now_s();
+      continue;
+    }
+    J.h = h;
+    J.slot = slot;
+    J.state = 1;
+    J.t_admit = now_s();
+    S->used += J.foot;
+    S->slots[slot] = J.id;
+    RunDev r{};
+    r.t = 0;
+    r.t_end = J.K;
+    r.active = 1;
+    r.hash = 0xcbf29ce484222325ull;
+    r.cur_step = -1;
+    S->runs[slot] = r;
+    S->dirty = true;
+    S->stats.admitted++;
+  }
+  HIPCHK(hipStreamSynchronize(S->cstream), (asi_sim*)nullptr);
+  return ASI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -960,16 +1026,30 @@ asi_status asi_server_create(const asi_device* dev, size_t hbm_budget_bytes, int
   auto* S = new (std::nothrow) asi_server();
   if (!S) return fail(ASI_ENOMEM, "host allocation failed");
   if (dev) S->dev = *dev;
-  S->dev.stream = nullptr;
   if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
     delete S;
     return fail(ASI_EDEVICE, "stream creation failed");
   }
+  if (hipStreamCreateWithFlags(&S->cstream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipStreamDestroy(S->stream);
+    delete S;
+    return fail(ASI_EDEVICE, "stream creation failed");
+  }
+  if (hipHostMalloc((void**)&S->rb, sizeof(RunDev) * max_slots, hipHostMallocDefault) !=
+      hipSuccess) {
+    (void)hipStreamDestroy(S->cstream);
+    (void)hipStreamDestroy(S->stream);
+    delete S;
+    return fail(ASI_ENOMEM, "pinned host allocation failed");
+  }
   S->dev.stream = S->stream;
+  S->cdev = S->dev;
+  S->cdev.stream = S->cstream;
   S->budget = hbm_budget_bytes;
   S->max_slots = max_slots;
   S->slots.assign(max_slots, -1);
   S->runs.assign(max_slots, RunDev{});
+  S->in_burst.assign(max_slots, 0);
   S->T.mem.dev = S->dev;
   {
     int dev_id = 0, khz = 0;
@@ -1009,71 +1089,56 @@ asi_status asi_server_submit(asi_server_t S, const asi_params* p, int64_t n_step
 asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out) {
   if (!S) return fail(ASI_EINVAL, "null server");
   if (!(budget_ms > 0.0)) return fail(ASI_EINVAL, "budget_ms must be > 0");
-  // admit in arrival order while a slot and the budget allow
-  while (!S->queue.empty()) {
-    int32_t slot = -1;
-    for (int32_t k = 0; k < S->max_slots; ++k)
-      if (S->slots[k] < 0) {
-        slot = k;
-        break;
-      }
-    if (slot < 0) break;
-    Job& J = *S->jobs[S->queue.front()];
-    if (S->used + J.foot > S->budget) break;
-    S->queue.pop_front();
-    asi_params p = J.p;
-    p.xy = J.xy.data();
-    p.theta = J.theta.data();
-    p.hk = J.hk.data();
-    p.spin0 = J.spin0.empty() ? nullptr : J.spin0.data();
-    asi_handle h = nullptr;
-    asi_status st = asi_create(&p, &S->dev, &h);
-    if (st == ASI_OK) st = asi_set_field_protocol(h, J.K, J.H.data());
-    if (st != ASI_OK) {
-      if (h) asi_destroy(h);
-      J.state = 3;
-      J.err = st;
-      J.t_done = now_s();
-      continue;
-    }
-    J.h = h;
-    J.slot = slot;
-    J.state = 1;
-    J.t_admit = now_s();
-    S->used += J.foot;
-    S->slots[slot] = J.id;
-    RunDev r{};
-    r.t = 0;
-    r.t_end = J.K;
-    r.active = 1;
-    r.hash = 0xcbf29ce484222325ull;
-    r.cur_step = -1;
-    S->runs[slot] = r;
-    S->dirty = true;
-  }
   int32_t resident = 0;
-  for (int32_t k = 0; k < S->max_slots; ++k) resident += S->slots[k] >= 0;
+  int64_t max_n = 0;
+  for (int32_t k = 0; k < S->max_slots; ++k) {
+    S->in_burst[k] = S->slots[k] >= 0;
+    if (S->slots[k] >= 0) {
+      ++resident;
+      max_n = std::max(max_n, S->jobs[S->slots[k]]->p.n);
+    }
+  }
+  // 1. launch a burst over the jobs resident now
   if (resident > 0) {
     if (S->dirty) {
+      const double t = now_s();
       asi_status st = server_rebuild(S);
       if (st != ASI_OK) return st;
+      S->stats.rebuild_s += now_s() - t;
     }
-    // one field launch (neighbour gathers of new jobs run grid-wide here),
-    // then every resident job advances through its own steps
-    const int64_t ticks = (int64_t)(budget_ms * 1e-3 * (double)S->clock_hz);
+    // The field launch covers every active job (new jobs' neighbour gathers
+    // run grid-wide here); then each job's workgroup relaxes and, outside the
+    // tail regime, goes on through its own later steps until the deadline.
+    const int64_t ticks = std::max<int64_t>(1, (int64_t)(budget_ms * 1e-3 * (double)S->clock_hz));
+    const bool tail = resident <= kTailJobs && max_n >= kTailMagnets;
     launch_field(S->T.dI, S->T.dR, S->T.blk_inst, S->T.blk_row0, S->T.nblocks, S->stream);
-    launch_fused(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, INT64_MAX, ticks, 1,
-                 S->stream);
-    HIPCHK(hipMemcpyAsync(S->runs.data(), S->T.dR, sizeof(RunDev) * S->max_slots,
-                          hipMemcpyDeviceToHost, S->stream),
+    launch_fused(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, tail ? 1 : INT64_MAX, ticks,
+                 1, S->stream);
+    HIPCHK(hipMemcpyAsync(S->rb, S->T.dR, sizeof(RunDev) * S->max_slots, hipMemcpyDeviceToHost,
+                          S->stream),
            (asi_sim*)nullptr);
+    S->stats.bursts++;
+  }
+  // 2. admission, while the burst runs
+  {
+    const double t = now_s();
+    asi_status st = server_admit(S);
+    S->stats.admit_s += now_s() - t;
+    if (st != ASI_OK) return st;
+  }
+  // 3. burst results: retire finished jobs
+  if (resident > 0) {
+    double t = now_s();
     HIPCHK(hipStreamSynchronize(S->stream), (asi_sim*)nullptr);
     HIPCHK(hipGetLastError(), (asi_sim*)nullptr);
-    // retire finished jobs
+    S->stats.wait_s += now_s() - t;
+    t = now_s();
     for (int32_t k = 0; k < S->max_slots; ++k) {
-      if (S->slots[k] < 0) continue;
+      if (!S->in_burst[k]) continue;
       RunDev& r = S->runs[k];
-      if (r.active) continue;
+      r = S->rb[k];
+      if (r.paused) S->stats.pauses++;
+      if (r.active || r.paused) continue;
       Job& J = *S->jobs[S->slots[k]];
       J.flips = r.flips;
       J.hash = r.hash;
@@ -1090,13 +1155,21 @@ asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out
       S->slots[k] = -1;
       S->runs[k] = RunDev{};
       S->dirty = true;
+      S->stats.retired++;
     }
+    S->stats.retire_s += now_s() - t;
   }
   if (active_out) {
     int32_t a = (int32_t)S->queue.size();
     for (int32_t k = 0; k < S->max_slots; ++k) a += S->slots[k] >= 0;
     *active_out = a;
   }
+  return ASI_OK;
+}
+
+asi_status asi_server_get_stats(asi_server_t S, asi_server_stats* out) {
+  if (!S || !out) return fail(ASI_EINVAL, "null argument");
+  *out = S->stats;
   return ASI_OK;
 }
 
@@ -1134,6 +1207,8 @@ asi_status asi_server_destroy(asi_server_t S) {
   S->jobs.clear();
   S->T.drop_graph();
   S->T.mem.release_all();
+  if (S->rb) (void)hipHostFree(S->rb);
+  (void)hipStreamDestroy(S->cstream);
   (void)hipStreamDestroy(S->stream);
   delete S;
   return ASI_OK;

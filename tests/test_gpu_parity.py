@@ -220,18 +220,28 @@ def test_batched_equals_plain_bitwise():
             assert np.array_equal(st[2], plain[k][1][2])
 
 
-def test_served_equals_plain_bitwise():
+@pytest.mark.parametrize("budget_ms", [20.0, 0.002])
+def test_served_equals_plain_bitwise(budget_ms):
+    # 0.002 ms is below one relax batch: nearly every burst pauses its relaxes
+    # mid-step, and each resumed relax must continue exactly where it stopped
     jobs = W.served_stream(count=10, seed=5, n_range=(200, 4000), steps_range=(20, 60))
-    say("served vs plain", [(j.family, j.n_target, j.d) for j in jobs])
+    say("served vs plain", budget_ms, [(j.family, j.n_target, j.d) for j in jobs])
     srv = asi.Server(hbm_budget_bytes=2 << 30, max_slots=4)
     ids = []
     pending = list(jobs)
     active = 1
+    calls = 0
     while pending or active:
         if pending:
             ids.append((pending[0], srv.submit(pending[0].workload())))
             pending.pop(0)
-        active = srv.step()
+        active = srv.step(budget_ms=budget_ms)
+        calls += 1
+    st = srv.stats()
+    say("server steps", calls, st)
+    assert st["admitted"] == st["retired"] == len(jobs) and st["bursts"] <= calls
+    if budget_ms < 0.01:
+        assert st["pauses"] > 0
     for job, jid in ids:
         assert srv.poll(jid)
         res = srv.take(jid)
