@@ -226,6 +226,10 @@ def bench_served(args, asi, workloads, torch):
     stats = srv.stats()
     srv.close()
     lats = np.array([lat[j.job] - j.arrival_s for j in jobs])
+    for j in sorted(jobs, key=lambda j: res[j.job]["t_admit"] - res[j.job]["t_done"])[:5]:
+        r = res[j.job]
+        progress(f"slow job {j.job} {j.family} n={wls[j.job].n} d={j.d:g} steps={j.n_steps} "
+                 f"flips={r['flips']} served={r['t_done'] - r['t_admit']:.3f}s")
     # plain rate from a seeded uniform sample, each job alone
     rng = np.random.default_rng(55)
     k = min(args.plain_sample, len(jobs))
@@ -245,6 +249,10 @@ def bench_served(args, asi, workloads, torch):
         s.close()
         times.append(time.perf_counter() - ts)
         same &= lg["hash"] == res[j.job]["hash"] and np.array_equal(spins, res[j.job]["spins"])
+        r = res[j.job]
+        progress(f"job {j.job} {j.family} n={w.n} d={j.d:g} steps={j.n_steps} "
+                 f"flips={lg['count']} plain={times[-1]:.3f}s "
+                 f"served={r['t_done'] - r['t_admit']:.3f}s")
         if c % 10 == 9:
             progress(f"plain sample {c + 1}/{k} {time.perf_counter() - t1:.1f}s")
     mean_plain = float(np.mean(times))

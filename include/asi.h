@@ -198,11 +198,12 @@ asi_status asi_server_submit(asi_server_t s, const asi_params* p, int64_t n_step
 /* Advance the server by one burst: run every resident job for about
  * budget_ms of device time (each job's workgroup advancing through its own
  * protocol; a relax still running at the deadline pauses mid-step and
- * resumes in the next burst), admit queued jobs that fit while the burst
- * runs (neighbour tables built at admission; they join the next burst), then
- * retire finished ones.  With few resident jobs, at least one of them large,
- * a burst is one field step of every job, with the field pass spread over the
- * whole device.  active_out (may be NULL): jobs still queued or resident. */
+ * resumes where it stopped), admit queued jobs that fit while the burst runs
+ * (neighbour tables built at admission; they join the next burst), then
+ * retire finished ones.  With at most 8 jobs resident, one of them large
+ * (>= 2^17 magnets), the burst is a sequence of rounds instead, each a field
+ * pass spread over the whole device and one relax step of every job.
+ * active_out (may be NULL): jobs still queued or resident. */
 asi_status asi_server_step(asi_server_t s, double budget_ms, int32_t* active_out);
 /* done_out = 1 when the job has finished (non-blocking). */
 asi_status asi_server_poll(asi_server_t s, int64_t job_id, int32_t* done_out);

@@ -74,6 +74,7 @@ struct InstDev {
   int32_t* ccount;        // entries in buffer 0 (field phase appends)
   int64_t ccap;
   int64_t spec_min;       // flippable magnets at step start to go speculative
+  double spec_switch;     // mean batch below which a speculative step goes on the tree
 };
 
 // Per-instance run cursor, device-resident so repeated launches (and
@@ -88,11 +89,11 @@ struct RunDev {
   uint64_t hash;      // running flip-log hash
   int64_t cur_step;   // last relaxed step
   // A relax stopped at a deadline part-way through step t leaves active = 0
-  // and paused = 1; its next fused launch rebuilds the relax structures from
-  // the key array and continues step t.  step_acc counts the flips step t
-  // has made so far.
+  // and paused = 1; the relax structures are rebuilt from the key array and
+  // step t continues on the same relax path (spec: speculative).  step_acc
+  // counts the flips step t has made so far.
   int32_t paused;
-  int32_t pad0;
+  int32_t spec;
   int64_t step_acc;
 };
 
@@ -105,17 +106,19 @@ void launch_neighbour_fill(const double* x, const double* y, const double* mx, c
                            const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,
                            double cut2, double alpha, int32_t D, int32_t* col, double* A,
                            double* B, double* Br, hipStream_t st);
-// Grid-wide field pass for every active instance of the table.
+// Grid-wide field pass for every active instance of the table; rebuilds the
+// relax structures of every paused one.
 void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,
                   const int32_t* blk_row0, int64_t nblocks, hipStream_t st);
 // One workgroup per instance: relax the current step.
 void launch_relax(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
                   size_t lds_bytes, hipStream_t st);
 // One workgroup per instance: up to max_steps whole steps (field phase and
-// relax) per instance.  With budget_ticks > 0 a workgroup stops once that
-// many ticks of the device's constant-rate clock have passed: between steps,
-// or inside a relax (which then pauses, see RunDev).  With first_ready the
-// fields of each active instance's first step were already computed.
+// relax) per instance.  With budget_ticks > 0 a workgroup stops once that many ticks of the
+// device's constant-rate clock have passed: between steps, or inside a relax
+// (which then pauses, see RunDev).  With first_ready a field launch has just
+// computed each active instance's fields and rebuilt each paused one's relax
+// structures.
 void launch_fused(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
                   size_t lds_bytes, int64_t max_steps, int64_t budget_ticks,
                   int32_t first_ready, hipStream_t st);

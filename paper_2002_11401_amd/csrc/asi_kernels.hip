@@ -332,16 +332,27 @@ __device__ __forceinline__ double field_row(const InstDev* __restrict__ I, int64
   return key;
 }
 
+// Key of row i as the state holds it, for an instance whose relax paused
+// mid-step: the relax keeps every key exact, so its candidate structures
+// are rebuilt from the key array instead of a field evaluation.
+__device__ __forceinline__ double stored_key(const InstDev* __restrict__ I, int64_t i,
+                                             uint32_t& payload) {
+  payload = (uint32_t)i | (I->s[i] < 0 ? 0x80000000u : 0u);
+  return I->key[i];
+}
+
 // Field phase for the 64 rows starting at row0 (a multiple of 64), by one
-// wavefront: rows, then their maximum key into the per-64-row table.
-// Returns the lane's (key, payload) for the candidate pool.
+// wavefront: rows (or, resuming a paused relax, their stored keys), then
+// their maximum key into the per-64-row table.  Returns the lane's (key,
+// payload) for the candidate pool.
 __device__ __forceinline__ double field_rows64(const InstDev* __restrict__ I, int64_t row0,
-                                               int64_t t, uint32_t& payload) {
+                                               int64_t t, uint32_t& payload,
+                                               bool resume = false) {
   const int lane = threadIdx.x & 63;
   const int64_t i = row0 + lane;
   double key = 0.0;
   payload = 0;
-  if (i < I->n) key = field_row(I, i, t, payload);
+  if (i < I->n) key = resume ? stored_key(I, i, payload) : field_row(I, i, t, payload);
   double mk = key;
   uint32_t mp = payload;
   wave_argmax(mk, mp);
@@ -369,9 +380,9 @@ __device__ __forceinline__ void pool_put(const InstDev* __restrict__ I, double k
 // Field phase by one wavefront, appending its flippable rows to the pool
 // with one atomic per wavefront.
 __device__ __forceinline__ void field_rows64_pool(const InstDev* __restrict__ I, int64_t row0,
-                                                  int64_t t) {
+                                                  int64_t t, bool resume = false) {
   uint32_t payload;
-  const double key = field_rows64(I, row0, t, payload);
+  const double key = field_rows64(I, row0, t, payload, resume);
   const unsigned long long bal = __ballot(key > 0.0);
   if (bal) {
     int base = 0;
@@ -382,7 +393,8 @@ __device__ __forceinline__ void field_rows64_pool(const InstDev* __restrict__ I,
 }
 
 // Grid-wide field pass: one lane per magnet, any number of instances; the
-// block's flippable rows reach the pool with one atomic per block.
+// block's flippable rows reach the pool with one atomic per block.  A paused
+// instance (see RunDev) gets its relax structures rebuilt instead.
 __global__ __launch_bounds__(kFieldBlock) void k_field(const InstDev* __restrict__ insts,
                                                       RunDev* __restrict__ runs,
                                                       const int32_t* __restrict__ blk_inst,
@@ -391,13 +403,14 @@ __global__ __launch_bounds__(kFieldBlock) void k_field(const InstDev* __restrict
   __shared__ int bbase;
   const int q = blk_inst[blockIdx.x];
   const RunDev* R = runs + q;
-  if (!R->active) return;
+  const bool resume = R->paused != 0;
+  if (!R->active && !resume) return;
   const InstDev* I = insts + q;
   const int wave = threadIdx.x >> 6;
   const int64_t wave_row0 = (int64_t)blk_row0[blockIdx.x] + wave * 64;
   uint32_t payload = 0;
   double key = 0.0;
-  if (wave_row0 < I->n) key = field_rows64(I, wave_row0, R->t, payload);
+  if (wave_row0 < I->n) key = field_rows64(I, wave_row0, R->t, payload, resume);
   const unsigned long long bal = __ballot(key > 0.0);
   if ((threadIdx.x & 63) == 0) wcount[wave] = __popcll(bal);
   __syncthreads();
@@ -512,6 +525,11 @@ constexpr int kMaxPairs = 2048;   // member + neighbour slots per batch
 constexpr int kMaxMembers = 64;
 // Above this degree a batch holds too few members to beat the max tree.
 constexpr int kSpecMaxD = 128;
+// A step whose first kSwitchBatches batches commit fewer than spec_switch
+// (2.5 unless overridden) flips each on average -- an avalanche: every flip
+// makes a neighbour the next candidate -- continues on the max tree, which
+// costs about half a batch per flip on such steps.
+constexpr int kSwitchBatches = 16;
 
 // Relax order of two magnets: larger key first, then lower index.
 __device__ inline bool better(double ka, uint32_t pa, double kb, uint32_t pb) {
@@ -805,8 +823,11 @@ __device__ inline uint32_t hash_slot(uint32_t i) { return (i * 2654435761u) >> (
 
 // Relax at step t in speculative batches (needs 1024 threads).  flips,
 // logpos and hash are the running counters (logpos and hash significant in
-// thread 0).  Returns 0, -5 (flip cap reached with a flippable magnet left)
-// or 1 (deadline passed after at least one batch, flippable magnets left).
+// thread 0).  Returns 0, -5 (flip cap reached with a flippable magnet left),
+// 1 (deadline passed after at least one batch, flippable magnets left) or
+// 2 (after kSwitchBatches batches the mean batch is below spec_switch flips:
+// the flippable magnets crowd each other's neighbourhoods, and the step
+// goes on one flip at a time).
 __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t t, unsigned char* lds,
                           SpecShared& sh, int64_t ncand, int64_t& flips, int64_t& logpos,
                           uint64_t& hash, uint64_t deadline) {
@@ -832,7 +853,12 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
   __syncthreads();
   int status = 0;
   const int64_t flips0 = flips;
+  int nbatch = 0;
   while (true) {
+    if (nbatch >= kSwitchBatches && (double)(flips - flips0) < I->spec_switch * nbatch) {
+      status = 2;
+      break;
+    }
     if (tid == 0) {
       sh.safe = count_safe(S, sh);
       sh.pause = (flips > flips0 && past(deadline)) ? 1 : 0;
@@ -1034,6 +1060,7 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
       }
     }
     flips += p;
+    ++nbatch;
     __syncthreads();
     // window entries consumed: up to the last committed member (stale ones
     // in between included), or the whole batch when every valid member went
@@ -1101,17 +1128,26 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
   const double pb = I->b, pc = I->c, ep = I->e_par, eq = I->e_perp;
   const int64_t max_flips = I->max_flips;
 
-  // first level from the per-64-row maxima of the field phase
+  // first level from the per-64-row maxima of the field phase (loads in
+  // groups of 8, issued together)
   for (int e = tid; e < nt1; e += NT) {
     double bk = 0.0;
     uint32_t bi = 0;
-    for (int u = 0; u < per0; ++u) {
-      const int64_t f = (int64_t)e * per0 + u;
-      if (f < nt0) {
-        const double k = I->t1key[f];
-        if (k > bk) {
-          bk = k;
-          bi = I->t1idx[f];
+    for (int u0 = 0; u0 < per0; u0 += 8) {
+      double kk[8];
+      uint32_t ki[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t f = (int64_t)e * per0 + u0 + u;
+        const bool ok = u0 + u < per0 && f < nt0;
+        kk[u] = ok ? I->t1key[f] : 0.0;
+        ki[u] = ok ? I->t1idx[f] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (kk[u] > bk) {
+          bk = kk[u];
+          bi = ki[u];
         }
       }
     }
@@ -1277,14 +1313,22 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
       const int64_t r0 = ((int64_t)e << l1s) + (int64_t)lane * seg;
       double bk = 0.0;
       uint32_t bp = 0;
-      for (int m = 0; m < seg; ++m) {
-        const int64_t ii = r0 + m;
-        if (ii < n) {
-          const double k = keyp[ii];
-          const int si = sp[ii];
-          if (k > bk) {
-            bk = k;
-            bp = (uint32_t)ii | (si < 0 ? 0x80000000u : 0u);
+      // the lane's segment in groups of 8, each group's loads issued together
+      for (int m0 = 0; m0 < seg; m0 += 8) {
+        double kk[8];
+        int ss[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int64_t ii = r0 + m0 + m;
+          const bool ok = m0 + m < seg && ii < n;
+          kk[m] = ok ? keyp[ii] : 0.0;
+          ss[m] = ok ? sp[ii] : 0;
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          if (kk[m] > bk) {
+            bk = kk[m];
+            bp = (uint32_t)(r0 + m0 + m) | (ss[m] < 0 ? 0x80000000u : 0u);
           }
         }
       }
@@ -1322,11 +1366,43 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
   return status;
 }
 
+// Per-64-row maxima of the stored keys -- the lowest level of the relax
+// tree -- rebuilt by the whole workgroup, four 64-row groups per wavefront
+// at a time (their loads issued together).
+__device__ __forceinline__ void rebuild_t1(const InstDev* __restrict__ I) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
+  const int64_t n = I->n, ng = (n + 63) >> 6;
+  for (int64_t g0 = (int64_t)wave * 4; g0 < ng; g0 += (int64_t)NW * 4) {
+    double k[4];
+    uint32_t p[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = ((g0 + u) << 6) + lane;
+      k[u] = 0.0;
+      p[u] = 0u;
+      if (g0 + u < ng && i < n) {
+        k[u] = I->key[i];
+        p[u] = (uint32_t)i | (I->s[i] < 0 ? 0x80000000u : 0u);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      wave_argmax(k[u], p[u]);
+      if (lane == 0 && g0 + u < ng) {
+        I->t1key[g0 + u] = k[u];
+        I->t1idx[g0 + u] = p[u];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Relax one instance at step t (Sec. II.H) and advance its run cursor.
 // Steps that start with at least spec_min flippable magnets (and a degree
 // that leaves room for batches) take the speculative path; the others the
-// max tree.  Both flip exactly the magnets, in exactly the order, of the
-// one-at-a-time relax.
+// max tree; a speculative step whose batches stay small continues on the
+// tree; a paused step resumes on the path it was on.  Both flip exactly the
+// magnets, in exactly the order, of the one-at-a-time relax.
 __device__ __forceinline__ int relax_step(const InstDev* __restrict__ I, RunDev* __restrict__ R, int64_t t,
                           unsigned char* lds_raw, RelaxShared& sh, SpecShared& ssh,
                           uint64_t deadline) {
@@ -1335,11 +1411,15 @@ __device__ __forceinline__ int relax_step(const InstDev* __restrict__ I, RunDev*
   int64_t flips = acc0;
   int64_t logpos = R->flips;
   uint64_t hash = R->hash;
-  int status;
-  if (blockDim.x == 1024 && I->D <= kSpecMaxD && ncand >= I->spec_min)
-    status = relax_spec(I, t, lds_raw, ssh, ncand, flips, logpos, hash, deadline);
-  else
+  bool spec = blockDim.x == 1024 &&
+              (R->paused ? R->spec != 0 : (I->D <= kSpecMaxD && ncand >= I->spec_min));
+  int status = 2;
+  if (spec) status = relax_spec(I, t, lds_raw, ssh, ncand, flips, logpos, hash, deadline);
+  if (status == 2) {
+    if (spec) rebuild_t1(I);  // the keys have moved since the field phase
+    spec = false;
     status = relax_tree(I, t, lds_raw, sh, flips, logpos, hash, deadline);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_store(I->ccount, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1349,6 +1429,7 @@ __device__ __forceinline__ int relax_step(const InstDev* __restrict__ I, RunDev*
     if (status == 1) {
       R->step_acc = flips;
       R->paused = 1;
+      R->spec = spec ? 1 : 0;
       R->active = 0;
     } else {
       if (t >= 0 && t < I->K && I->step_flips) I->step_flips[t] = (int32_t)flips;
@@ -1362,34 +1443,6 @@ __device__ __forceinline__ int relax_step(const InstDev* __restrict__ I, RunDev*
   }
   __syncthreads();
   return status;
-}
-
-// Relax structures of a paused instance, rebuilt from its state: the
-// per-64-row maxima of the exact keys and a fresh candidate pool (entries
-// carry the current versions), as its field phase would have left them.
-__device__ __forceinline__ void resume_rows64(const InstDev* __restrict__ I, int64_t row0) {
-  const int lane = threadIdx.x & 63;
-  const int64_t i = row0 + lane;
-  double key = 0.0;
-  uint32_t payload = 0;
-  if (i < I->n) {
-    key = I->key[i];
-    payload = (uint32_t)i | (I->s[i] < 0 ? 0x80000000u : 0u);
-  }
-  double mk = key;
-  uint32_t mp = payload;
-  wave_argmax(mk, mp);
-  if (lane == 0) {
-    I->t1key[row0 >> 6] = mk;
-    I->t1idx[row0 >> 6] = mp;
-  }
-  const unsigned long long bal = __ballot(key > 0.0);
-  if (bal) {
-    int base = 0;
-    if (lane == 0) base = atomicAdd(I->ccount, __popcll(bal));
-    base = __builtin_amdgcn_readfirstlane(base);
-    pool_put(I, key, payload, bal, base);
-  }
 }
 
 __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __restrict__ insts,
@@ -1407,9 +1460,10 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
 // instances never wait for each other between steps.  Stops after max_steps
 // steps, at the end of the protocol, on ELOOP, or once budget_ticks of the
 // constant-rate device clock have passed: checked between steps and inside
-// the relax, which then pauses mid-step.  A paused instance first rebuilds
-// its relax structures and finishes the step it stopped in; the flips it
-// makes, and their order, are those of an uninterrupted relax.
+// the relax, which then pauses mid-step.  A paused instance finishes the
+// step it stopped in first, its relax structures rebuilt (by the preceding
+// field launch when first_ready); the flips it makes, and their order, are
+// those of an uninterrupted relax.
 __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_fused(const InstDev* __restrict__ insts,
                                                               RunDev* __restrict__ runs,
                                                               int64_t max_steps,
@@ -1427,9 +1481,9 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_fused(const InstDev* __
   const uint64_t t_start = wall_clock64();
   const uint64_t deadline = budget_ticks > 0 ? t_start + (uint64_t)budget_ticks : 0;
   bool ready = first_ready != 0;
-  if (paused) {
+  if (paused && !ready) {
     for (int64_t row0 = (int64_t)wave * 64; row0 < I->n; row0 += (int64_t)NW * 64)
-      resume_rows64(I, row0);
+      field_rows64_pool(I, row0, R->t, true);
     __syncthreads();
     ready = true;
   }

@@ -428,6 +428,8 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   HIPCHK(hipMemsetAsync(I.ccount, 0, 4, s->stream), s);
   I.spec_min = 32;
   if (const char* e = std::getenv("ASI_SPEC_MIN")) I.spec_min = std::atoll(e);
+  I.spec_switch = 2.5;
+  if (const char* e = std::getenv("ASI_SPEC_SWITCH")) I.spec_switch = std::atof(e);
   s->dI = dalloc<InstDev>(s, 1);
   s->dR = dalloc<RunDev>(s, 1);
   s->nblocks = (n + kFieldBlock - 1) / kFieldBlock;
@@ -926,17 +928,20 @@ struct asi_server {
   RunDev* rb = nullptr;         // pinned read-back of the burst's cursors
   std::vector<char> in_burst;   // slot took part in the running burst
   int64_t clock_hz = 100000000;  // device constant-rate clock
+  int64_t big_magnets = 0;       // see kBigMagnets
+  int32_t tail_jobs = 0;         // see kTailJobs
   asi_server_stats stats{};
 };
 
 namespace {
 
-// A burst runs one field step per job (grid-wide field pass, then the
-// relaxes) instead of per-workgroup protocols when at most this many jobs are
-// resident and one of them has at least kTailMagnets magnets: a lone large
-// job's field phase would otherwise stream through a single compute unit.
+// Inside the fused kernel a job's field phase streams through a single
+// compute unit.  When at most kTailJobs jobs are resident and one has at
+// least kBigMagnets magnets, the device is mostly idle and that phase would
+// dominate: such a burst is a sequence of rounds, each a grid-wide field pass
+// and one relax step of every job, until the budget is spent.
+constexpr int64_t kBigMagnets = 1 << 17;
 constexpr int32_t kTailJobs = 8;
-constexpr int64_t kTailMagnets = 1 << 16;
 
 asi_status server_rebuild(asi_server* S) {
   std::vector<InstDev> insts(S->max_slots);
@@ -1051,6 +1056,16 @@ asi_status asi_server_create(const asi_device* dev, size_t hbm_budget_bytes, int
   S->runs.assign(max_slots, RunDev{});
   S->in_burst.assign(max_slots, 0);
   S->T.mem.dev = S->dev;
+  S->big_magnets = kBigMagnets;
+  S->tail_jobs = kTailJobs;
+  if (const char* v = std::getenv("ASI_SERVER_BIG")) {  // threshold overrides
+    const long long b = std::atoll(v);
+    if (b >= 1) S->big_magnets = b;
+  }
+  if (const char* v = std::getenv("ASI_SERVER_TAIL")) {
+    const int b = std::atoi(v);
+    if (b >= 0) S->tail_jobs = b;
+  }
   {
     int dev_id = 0, khz = 0;
     if (hipGetDevice(&dev_id) == hipSuccess &&
@@ -1091,6 +1106,8 @@ asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out
   if (!(budget_ms > 0.0)) return fail(ASI_EINVAL, "budget_ms must be > 0");
   int32_t resident = 0;
   int64_t max_n = 0;
+  bool tail = false;
+  double t_end = 0.0;
   for (int32_t k = 0; k < S->max_slots; ++k) {
     S->in_burst[k] = S->slots[k] >= 0;
     if (S->slots[k] >= 0) {
@@ -1107,16 +1124,20 @@ asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out
       S->stats.rebuild_s += now_s() - t;
     }
     // The field launch covers every active job (new jobs' neighbour gathers
-    // run grid-wide here); then each job's workgroup relaxes and, outside the
-    // tail regime, goes on through its own later steps until the deadline.
+    // run grid-wide here) and rebuilds paused relaxes; then each job's
+    // workgroup relaxes and goes on through its later steps until the
+    // deadline.  In the tail regime the first round is launched here, the
+    // others after admission.
+    const double t_burst = now_s();
     const int64_t ticks = std::max<int64_t>(1, (int64_t)(budget_ms * 1e-3 * (double)S->clock_hz));
-    const bool tail = resident <= kTailJobs && max_n >= kTailMagnets;
+    tail = resident <= S->tail_jobs && max_n >= S->big_magnets;
     launch_field(S->T.dI, S->T.dR, S->T.blk_inst, S->T.blk_row0, S->T.nblocks, S->stream);
     launch_fused(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, tail ? 1 : INT64_MAX, ticks,
                  1, S->stream);
     HIPCHK(hipMemcpyAsync(S->rb, S->T.dR, sizeof(RunDev) * S->max_slots, hipMemcpyDeviceToHost,
                           S->stream),
            (asi_sim*)nullptr);
+    t_end = t_burst + budget_ms * 1e-3;
     S->stats.bursts++;
   }
   // 2. admission, while the burst runs
@@ -1131,6 +1152,23 @@ asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out
     double t = now_s();
     HIPCHK(hipStreamSynchronize(S->stream), (asi_sim*)nullptr);
     HIPCHK(hipGetLastError(), (asi_sim*)nullptr);
+    // tail regime: one more step of every job per round, each relax allowed
+    // to run to the end of the burst's budget
+    while (tail) {
+      bool more = false;
+      for (int32_t k = 0; k < S->max_slots; ++k)
+        if (S->in_burst[k] && S->rb[k].active) more = true;
+      const double left = t_end - now_s();
+      if (!more || left <= 0.0) break;
+      const int64_t ticks = std::max<int64_t>(1, (int64_t)(left * (double)S->clock_hz));
+      launch_field(S->T.dI, S->T.dR, S->T.blk_inst, S->T.blk_row0, S->T.nblocks, S->stream);
+      launch_fused(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, 1, ticks, 1, S->stream);
+      HIPCHK(hipMemcpyAsync(S->rb, S->T.dR, sizeof(RunDev) * S->max_slots,
+                            hipMemcpyDeviceToHost, S->stream),
+             (asi_sim*)nullptr);
+      HIPCHK(hipStreamSynchronize(S->stream), (asi_sim*)nullptr);
+      HIPCHK(hipGetLastError(), (asi_sim*)nullptr);
+    }
     S->stats.wait_s += now_s() - t;
     t = now_s();
     for (int32_t k = 0; k < S->max_slots; ++k) {

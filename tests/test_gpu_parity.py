@@ -220,13 +220,20 @@ def test_batched_equals_plain_bitwise():
             assert np.array_equal(st[2], plain[k][1][2])
 
 
-@pytest.mark.parametrize("budget_ms", [20.0, 0.002])
-def test_served_equals_plain_bitwise(budget_ms):
-    # 0.002 ms is below one relax batch: nearly every burst pauses its relaxes
-    # mid-step, and each resumed relax must continue exactly where it stopped
-    jobs = W.served_stream(count=10, seed=5, n_range=(200, 4000), steps_range=(20, 60))
-    say("served vs plain", budget_ms, [(j.family, j.n_target, j.d) for j in jobs])
-    srv = asi.Server(hbm_budget_bytes=2 << 30, max_slots=4)
+@pytest.mark.parametrize("budget_ms,big,slots,count", [
+    (20.0, None, 4, 10),
+    (0.002, None, 4, 10),   # below one relax batch: nearly every relax pauses
+    (0.05, 1500, 4, 10),    # rounds, every job one step per round
+    (0.05, 1500, 12, 24),   # rounds, jobs >= 1500 magnets one step per round
+])
+def test_served_equals_plain_bitwise(budget_ms, big, slots, count, monkeypatch):
+    # paused relaxes must continue exactly where they stopped, whether their
+    # structures are rebuilt by the grid-wide pass or inside the fused kernel
+    if big is not None:
+        monkeypatch.setenv("ASI_SERVER_BIG", str(big))
+    jobs = W.served_stream(count=count, seed=5, n_range=(200, 4000), steps_range=(20, 60))
+    say("served vs plain", budget_ms, big, slots, [(j.family, j.n_target, j.d) for j in jobs])
+    srv = asi.Server(hbm_budget_bytes=2 << 30, max_slots=slots)
     ids = []
     pending = list(jobs)
     active = 1
