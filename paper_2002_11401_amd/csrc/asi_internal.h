@@ -32,13 +32,18 @@ struct InstDev {
   int64_t n;              // magnets
   int32_t D;              // padded row length of the neighbour tables
   int32_t l1_shift;       // log2 of the first-level tile size of the relax tree
-  // Neighbour tables, sliced: slot k of row i lives at
-  //   ((i / 64) * D + k) * 64 + (i % 64);  col == -1 pads a row.
+  // Neighbour tables, sliced for the field pass (one row per lane): slot k
+  // of row i lives at ((i / 64) * D + k) * 64 + (i % 64);  col == -1 pads a
+  // row.
   const int32_t* len;     // [n] neighbours of each row
   const int32_t* col;     // neighbour index j (ascending within a row)
   const double* A;        // mhat_i    . c_ij  (symmetric: A_ij == A_ji)
   const double* B;        // mhatperp_i. c_ij  (field at row i from j)
-  const double* Br;       // mhatperp_j. c_ji  (field at neighbour j from row i)
+  // The same rows row-major for the relax, which walks one row at a time
+  // (a wavefront reads consecutive slots): slot k of row i at i * D + k.
+  const int32_t* rcol;    // neighbour index j, -1 pads
+  const double* rA;       // A_ij
+  const double* rBr;      // mhatperp_j. c_ji  (field at neighbour j from row i)
   const double* mx;       // [n] easy axis mhat_i = (mx, my)
   const double* my;
   const double* hk;       // [n] coercive field h_k^(i)
@@ -105,7 +110,7 @@ void launch_neighbour_fill(const double* x, const double* y, const double* mx, c
                            const int32_t* cellx, const int32_t* celly, const int32_t* cell_start,
                            const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,
                            double cut2, double alpha, int32_t D, int32_t* col, double* A,
-                           double* B, double* Br, hipStream_t st);
+                           double* B, int32_t* rcol, double* rA, double* rBr, hipStream_t st);
 // Grid-wide field pass for every active instance of the table; rebuilds the
 // relax structures of every paused one.
 void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,

@@ -68,15 +68,27 @@ __device__ inline void thermal_normals(uint64_t seed, uint32_t i, uint32_t t, do
   z1 = rad * sn;
 }
 
+// Upper bound of x^e (x >= 0, e > 0) from the single-precision hardware
+// log2 and exp2, inflated by 0.1 %, far past their error (a few units in
+// the 24th bit of the exponent and of the result); x below 2^-100 is raised
+// to 2^-100, which only raises x^e.
+__device__ inline float pow_bound(double x, double e) {
+  const float xf = (float)fmax(x, 0x1p-100);
+  return __builtin_amdgcn_exp2f((float)e * __builtin_amdgcn_logf(xf)) * 1.001f;
+}
+
 // Switching key: the left-hand side of Eq. 5 when magnet i may flip, i.e.
 // the field opposes the moment (Eq. 6, s_i h_par < 0) and Eq. 5 exceeds 1;
-// otherwise 0.  Exponents ep = 2/gamma, eq = 2/beta.
+// otherwise 0.  Exponents ep = 2/gamma, eq = 2/beta.  When the bound puts
+// the left-hand side below 0.99 the FP64 powers (which could only give a
+// value <= 1) are skipped: the key is the same, bit for bit.
 __device__ inline double switching_key(int s, double hp, double hq, double hk, double b,
                                        double c, double ep, double eq) {
   const bool against = (s > 0) ? (hp < 0.0) : (hp > 0.0);
   if (!against) return 0.0;
   const double a = fabs(hp) / (b * hk);
   const double q = fabs(hq) / (c * hk);
+  if (pow_bound(a, ep) + pow_bound(q, eq) < 0.99f) return 0.0;
   const double L = pow(a, ep) + pow(q, eq);
   return (L > 1.0) ? L : 0.0;
 }
@@ -183,14 +195,16 @@ __global__ void k_nb_count(const double* __restrict__ x, const double* __restric
 
 // Fills row i in ascending neighbour order by a 9-way merge of the
 // (ascending) member lists of its 3 x 3 cell block, and computes the
-// projected couplings of each pair.
+// projected couplings of each pair; writes the sliced and the row-major
+// tables.
 __global__ void k_nb_fill(const double* __restrict__ x, const double* __restrict__ y,
                           const double* __restrict__ mx, const double* __restrict__ my,
                           const int32_t* __restrict__ cellx, const int32_t* __restrict__ celly,
                           const int32_t* __restrict__ cstart, const int32_t* __restrict__ cmem,
                           int64_t n, int64_t gx, int64_t gy, double cut2, double alpha,
                           int32_t D, int32_t* __restrict__ col, double* __restrict__ A,
-                          double* __restrict__ B, double* __restrict__ Br) {
+                          double* __restrict__ B, int32_t* __restrict__ rcol,
+                          double* __restrict__ rA, double* __restrict__ rBr) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double xi = x[i], yi = y[i], mxi = mx[i], myi = my[i];
@@ -238,7 +252,10 @@ __global__ void k_nb_fill(const double* __restrict__ x, const double* __restrict
     col[sl] = j;
     A[sl] = a;
     B[sl] = b;
-    Br[sl] = bt;
+    const int64_t rs = i * D + k;
+    rcol[rs] = j;
+    rA[rs] = a;
+    rBr[rs] = bt;
     ++k;
   }
   for (; k < D; ++k) {
@@ -246,7 +263,10 @@ __global__ void k_nb_fill(const double* __restrict__ x, const double* __restrict
     col[sl] = -1;
     A[sl] = 0.0;
     B[sl] = 0.0;
-    Br[sl] = 0.0;
+    const int64_t rs = i * D + k;
+    rcol[rs] = -1;
+    rA[rs] = 0.0;
+    rBr[rs] = 0.0;
   }
 }
 
@@ -898,10 +918,10 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
         if (k == D) {
           pr_i[u] = (int)j;
         } else {
-          const int64_t sl = slot_of(j, D, k);
-          pr_i[u] = I->col[sl];
-          pr_a[u] = I->A[sl];
-          pr_b[u] = I->Br[sl];
+          const int64_t sl = (int64_t)j * D + k;
+          pr_i[u] = I->rcol[sl];
+          pr_a[u] = I->rA[sl];
+          pr_b[u] = I->rBr[sl];
         }
       }
     }
@@ -1113,9 +1133,9 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
   RelaxLds L = carve(lds_raw, nt1, nt2);
 
   const int32_t D = I->D;
-  const int32_t* __restrict__ colp = I->col;
-  const double* __restrict__ Ap = I->A;
-  const double* __restrict__ Brp = I->Br;
+  const int32_t* __restrict__ colp = I->rcol;
+  const double* __restrict__ Ap = I->rA;
+  const double* __restrict__ Brp = I->rBr;
   const double* __restrict__ hkp = I->hk;
   int8_t* __restrict__ sp = I->s;
   double* __restrict__ hpp = I->h_par;
@@ -1243,7 +1263,7 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
 #pragma unroll
     for (int h = 0; h < 2; ++h) u_i[h] = -1;
     for (int k = tid, h = 0; k < D; k += NT, ++h) {
-      const int64_t sl = slot_of(j, D, k);
+      const int64_t sl = j * D + k;
       const int32_t i = colp[sl];
       if (i >= 0) {
         const double da = two * Ap[sl], db = two * Brp[sl];
@@ -1538,11 +1558,13 @@ void launch_neighbour_fill(const double* x, const double* y, const double* mx, c
                            const int32_t* cellx, const int32_t* celly, const int32_t* cell_start,
                            const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,
                            double cut2, double alpha, int32_t D, int32_t* col, double* A,
-                           double* B, double* Br, hipStream_t st) {
+                           double* B, int32_t* rcol, double* rA, double* rBr,
+                           hipStream_t st) {
   const int bs = 128;
   const int64_t nb = (n + bs - 1) / bs;
   hipLaunchKernelGGL(k_nb_fill, dim3((unsigned)nb), dim3(bs), 0, st, x, y, mx, my, cellx, celly,
-                     cell_start, cell_members, n, gx, gy, cut2, alpha, D, col, A, B, Br);
+                     cell_start, cell_members, n, gx, gy, cut2, alpha, D, col, A, B, rcol, rA,
+                     rBr);
 }
 
 void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,

@@ -240,7 +240,7 @@ T* dalloc(asi_sim* s, size_t count) {
 size_t footprint_estimate(int64_t n, int64_t D, int64_t K, int64_t log_cap) {
   const int64_t nsl = (n + kSlice - 1) / kSlice;
   size_t slots = (size_t)nsl * kSlice * (size_t)D;
-  size_t b = slots * (4 + 8 + 8 + 8);
+  size_t b = slots * (4 + 8 + 8) + (size_t)n * (size_t)std::max<int64_t>(D, 1) * (4 + 8 + 8);
   b += (size_t)n * (4 + 8 + 8 + 8 + 1 + 1 + 8 * 7 + 4) + (size_t)(n + 8192) * 32;
   b += (size_t)nsl * 12 + (size_t)log_cap * 8 + (size_t)K * 20;
   b += 1 << 16;
@@ -352,16 +352,25 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   int32_t* dcol = dalloc<int32_t>(s, slots);
   double* dA = dalloc<double>(s, slots);
   double* dB = dalloc<double>(s, slots);
-  double* dBr = dalloc<double>(s, slots);
-  if (!dcol || !dA || !dB || !dBr) return fail(ASI_ENOMEM, "device allocation failed (neighbour tables)");
+  // row-major copy for the relax (every slot written by the fill)
+  const size_t rslots = (size_t)n * (size_t)std::max(D, 1);
+  int32_t* drcol = dalloc<int32_t>(s, rslots);
+  double* drA = dalloc<double>(s, rslots);
+  double* drBr = dalloc<double>(s, rslots);
+  if (!dcol || !dA || !dB || !drcol || !drA || !drBr)
+    return fail(ASI_ENOMEM, "device allocation failed (neighbour tables)");
   // rows of a partial last slice stay padded
   HIPCHK(hipMemsetAsync(dcol, 0xff, 4 * slots, s->stream), s);
   HIPCHK(hipMemsetAsync(dA, 0, 8 * slots, s->stream), s);
   HIPCHK(hipMemsetAsync(dB, 0, 8 * slots, s->stream), s);
-  HIPCHK(hipMemsetAsync(dBr, 0, 8 * slots, s->stream), s);
+  if (D == 0) {
+    HIPCHK(hipMemsetAsync(drcol, 0xff, 4 * rslots, s->stream), s);
+    HIPCHK(hipMemsetAsync(drA, 0, 8 * rslots, s->stream), s);
+    HIPCHK(hipMemsetAsync(drBr, 0, 8 * rslots, s->stream), s);
+  }
   if (D > 0)
     launch_neighbour_fill(dx, dy, dmx, dmy, dcx, dcy, dcs, dcm, n, gx, gy, cut2, p->alpha, D, dcol,
-                          dA, dB, dBr, s->stream);
+                          dA, dB, drcol, drA, drBr, s->stream);
   HIPCHK(hipStreamSynchronize(s->stream), s);
   s->mem.release(dcx);
   s->mem.release(dcy);
@@ -386,7 +395,9 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   I.col = dcol;
   I.A = dA;
   I.B = dB;
-  I.Br = dBr;
+  I.rcol = drcol;
+  I.rA = drA;
+  I.rBr = drBr;
   I.mx = dmx;
   I.my = dmy;
   I.hk = dhk;
