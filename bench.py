@@ -293,7 +293,7 @@ def main():
     ap.add_argument("--rate", type=float, default=50.0, help="served: arrivals per second")
     ap.add_argument("--max-n", type=float, default=1e6, help="served: largest job")
     ap.add_argument("--slots", type=int, default=256, help="served: resident jobs")
-    ap.add_argument("--budget-gb", type=float, default=200.0, help="served: HBM budget")
+    ap.add_argument("--budget-gb", type=float, default=240.0, help="served: HBM budget")
     ap.add_argument("--burst-ms", type=float, default=20.0, help="served: device time per step")
     args = ap.parse_args()
     if args.gpus != 1:

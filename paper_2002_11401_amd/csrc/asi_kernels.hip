@@ -82,15 +82,25 @@ __device__ inline float pow_bound(double x, double e) {
 // otherwise 0.  Exponents ep = 2/gamma, eq = 2/beta.  When the bound puts
 // the left-hand side below 0.99 the FP64 powers (which could only give a
 // value <= 1) are skipped: the key is the same, bit for bit.
-__device__ inline double switching_key(int s, double hp, double hq, double hk, double b,
-                                       double c, double ep, double eq) {
+// In two stages: key_needs_powers settles the key at 0, or gives the
+// normalised field components a and q whose powers decide it.
+__device__ inline bool key_needs_powers(int s, double hp, double hq, double hk, double b,
+                                        double c, double ep, double eq, double& a, double& q) {
   const bool against = (s > 0) ? (hp < 0.0) : (hp > 0.0);
-  if (!against) return 0.0;
-  const double a = fabs(hp) / (b * hk);
-  const double q = fabs(hq) / (c * hk);
-  if (pow_bound(a, ep) + pow_bound(q, eq) < 0.99f) return 0.0;
+  if (!against) return false;
+  a = fabs(hp) / (b * hk);
+  q = fabs(hq) / (c * hk);
+  return !(pow_bound(a, ep) + pow_bound(q, eq) < 0.99f);
+}
+__device__ inline double key_from_powers(double a, double q, double ep, double eq) {
   const double L = pow(a, ep) + pow(q, eq);
   return (L > 1.0) ? L : 0.0;
+}
+__device__ inline double switching_key(int s, double hp, double hq, double hk, double b,
+                                       double c, double ep, double eq) {
+  double a = 0.0, q = 0.0;
+  if (!key_needs_powers(s, hp, hq, hk, b, c, ep, eq, a, q)) return 0.0;
+  return key_from_powers(a, q, ep, eq);
 }
 
 // Eq. 3 for a unit source moment mhat_s at (sx, sy) seen at (fx, fy),
@@ -619,7 +629,7 @@ __device__ inline SpecLds carve_spec(unsigned char* base) {
 }
 
 struct SpecShared {
-  int nx, xb, ns, nvalid, p, safe, cb, pause;
+  int nx, xb, ns, nvalid, p, safe, cb, pause, npow;
   int64_t ncold, ncold_out, napp;
   double cmk;       // cold_max (key, payload, version); key -1: pool empty
   uint32_t cmp, cmv;
@@ -861,6 +871,10 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
   const int PW = D + 1;  // pair slots per member: its neighbours and itself
   int Bmax = kMaxPairs / PW;
   if (Bmax > kMaxMembers) Bmax = kMaxMembers;
+  // Members taken per batch: about twice the last committed prefix, since
+  // the members past the prefix only cost loads and key evaluations;
+  // doubled while whole batches commit.
+  int bcap = Bmax;
   if (tid == 0) {
     sh.nx = 0;
     sh.xb = 0;
@@ -896,7 +910,7 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
       status = 1;
       break;
     }
-    const int B = sh.safe < Bmax ? sh.safe : Bmax;
+    const int B = sh.safe < bcap ? sh.safe : bcap;
     const int xb = sh.xb;
     const double* xk = win_k(S, xb);
     const uint32_t* xp = win_p(S, xb);
@@ -946,6 +960,7 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
         sh.p = __popcll(bal);
         sh.ns = 0;
         sh.napp = 0;
+        sh.npow = 0;
       }
     }
     __syncthreads();
@@ -982,13 +997,24 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
     }
     __syncthreads();
     const int p_ab = sh.p;
-    // ---- round trip 2: touched magnets of the conflict-free prefix
+    // ---- round trip 2: touched magnets of the conflict-free prefix.  Keys
+    // the switching bound cannot settle go through a dense list in LDS
+    // (aliasing the conflict table, done with), so that the FP64 powers run
+    // on full wavefronts.
     double nh_p[kPPT], nh_q[kPPT], nkey[kPPT], nd_p[kPPT], nd_q[kPPT];
     uint32_t nver[kPPT];
-    int nsi[kPPT];
+    int nsi[kPPT], ppos[kPPT];
+    double* pw_a = S.sk;            // kMaxPairs doubles
+    double* pw_q = (double*)S.sp;   // kMaxPairs doubles (sp and sv)
+    double pa[kPPT], pq[kPPT];
+    bool need[kPPT];
 #pragma unroll
-    for (int u = 0; u < kPPT; ++u) {
+    for (int u = 0; u < kPPT; ++u) {  // all gathers first: one round trip
       nkey[u] = 0.0;
+      ppos[u] = -1;
+      pa[u] = 0.0;
+      pq[u] = 0.0;
+      need[u] = false;
       const int k = (pr_m[u] >= 0) ? (tid + u * NT) % PW : D;
       if (pr_r[u] >= 0 && pr_r[u] < p_ab && k < D) {
         const int i = pr_i[u];
@@ -1003,7 +1029,32 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
         }
         nsi[u] = I->s[i];
         nver[u] = I->ver[i];
-        nkey[u] = switching_key(nsi[u], nh_p[u], nh_q[u], I->hk[i], pb, pc, ep, eq);
+        need[u] = key_needs_powers(nsi[u], nh_p[u], nh_q[u], I->hk[i], pb, pc, ep, eq, pa[u],
+                                   pq[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kPPT; ++u) {
+      const unsigned long long bal = __ballot(need[u]);
+      if (bal) {
+        int base = 0;
+        if ((tid & 63) == 0) base = atomicAdd(&sh.npow, __popcll(bal));
+        base = __builtin_amdgcn_readfirstlane(base);
+        if (need[u]) {
+          ppos[u] = base + __popcll(bal & ((1ull << (tid & 63)) - 1ull));
+          pw_a[ppos[u]] = pa[u];
+          pw_q[ppos[u]] = pq[u];
+        }
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < sh.npow; e += NT) pw_a[e] = key_from_powers(pw_a[e], pw_q[e], ep, eq);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPPT; ++u) {
+      if (ppos[u] >= 0) {
+        nkey[u] = pw_a[ppos[u]];
+        const int i = pr_i[u];
         if (nkey[u] > 0.0) {
           // first later member of the prefix this magnet would beat
           const uint32_t npay = (uint32_t)i | (nsi[u] < 0 ? 0x80000000u : 0u);
@@ -1047,9 +1098,14 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
     const uint32_t cmp = sh.cmp, cmv = sh.cmv;
     const int cb = sh.cb;
     const int64_t ncold = sh.ncold;
+    // flippable touched magnets go to staging (if they may enter the window)
+    // or to the cold pool, with one LDS atomic per wavefront for each
+    const unsigned long long lt = (1ull << (tid & 63)) - 1ull;
 #pragma unroll
     for (int u = 0; u < kPPT; ++u) {
       const int k = (pr_m[u] >= 0) ? (tid + u * NT) % PW : D;
+      bool st = false, co = false;
+      uint32_t npay = 0, v1 = 0;
       if (pr_r[u] >= 0 && pr_r[u] < p && k < D) {
         const int i = pr_i[u];
         I->h_par[i] = nh_p[u];
@@ -1061,26 +1117,40 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
           I->dirty[i] = 1;
         }
         I->key[i] = nkey[u];
-        const uint32_t v1 = nver[u] + 1u;
+        v1 = nver[u] + 1u;
         I->ver[i] = v1;
         if (nkey[u] > 0.0) {
-          const uint32_t npay = (uint32_t)i | (nsi[u] < 0 ? 0x80000000u : 0u);
-          if (better_e(nkey[u], npay, v1, cmk, cmp, cmv)) {
-            const int q = atomicAdd(&sh.ns, 1);
-            S.sk[q] = nkey[u];
-            S.sp[q] = npay;
-            S.sv[q] = v1;
-          } else {
-            const int64_t q = ncold + atomicAdd((unsigned long long*)&sh.napp, 1ull);
-            I->ckey[cb][q] = nkey[u];
-            I->cpay[cb][q] = npay;
-            I->cver[cb][q] = v1;
-          }
+          npay = (uint32_t)i | (nsi[u] < 0 ? 0x80000000u : 0u);
+          st = better_e(nkey[u], npay, v1, cmk, cmp, cmv);
+          co = !st;
         }
+      }
+      const unsigned long long bs = __ballot(st), bc = __ballot(co);
+      int sbase = 0, cbase = 0;
+      if ((tid & 63) == 0) {
+        if (bs) sbase = atomicAdd(&sh.ns, __popcll(bs));
+        if (bc) cbase = (int)atomicAdd((unsigned long long*)&sh.napp, (unsigned long long)__popcll(bc));
+      }
+      sbase = __builtin_amdgcn_readfirstlane(sbase);
+      cbase = __builtin_amdgcn_readfirstlane(cbase);
+      if (st) {
+        const int q = sbase + __popcll(bs & lt);
+        S.sk[q] = nkey[u];
+        S.sp[q] = npay;
+        S.sv[q] = v1;
+      }
+      if (co) {
+        const int64_t q = ncold + cbase + __popcll(bc & lt);
+        I->ckey[cb][q] = nkey[u];
+        I->cpay[cb][q] = npay;
+        I->cver[cb][q] = v1;
       }
     }
     flips += p;
     ++nbatch;
+    bcap = (p >= B) ? 2 * B : 2 * p + 2;
+    if (bcap < 8) bcap = 8;
+    if (bcap > Bmax) bcap = Bmax;
     __syncthreads();
     // window entries consumed: up to the last committed member (stale ones
     // in between included), or the whole batch when every valid member went
