@@ -154,6 +154,18 @@ def bench_batched(args, asi, workloads, torch):
     sims = [asi.Sim.from_workload(w) for w in ws]
     ntot = sum(w.n for w in ws)
     etot = sum(s.info()["n_edges"] for s in sims)
+    # autotuned launch shapes per instance (state restored exactly), used by
+    # both the sequential and the batched runs
+    shapes = {}
+    t_tune = 0.0
+    if args.tune_steps > 0:
+        t0 = time.perf_counter()
+        for s in sims:
+            r = s.tune(args.tune_steps)
+            key = f"waves{r['relax_waves']}/l1s{r['l1_shift']}/spec_min{min(r['spec_min'], 10**9)}"
+            shapes[key] = shapes.get(key, 0) + 1
+        t_tune = time.perf_counter() - t0
+        progress(f"tuned {len(sims)} instances in {t_tune:.1f}s: {shapes}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain = []
@@ -185,7 +197,8 @@ def bench_batched(args, asi, workloads, torch):
                        "parallelism": "one launch per phase over all instances"},
             "batched_runs_per_s": len(ws) / t_bat, "plain_runs_per_s": len(ws) / t_seq,
             "speedup_vs_plain": t_seq / t_bat, "plain_seconds": t_seq, "batched_seconds": t_bat,
-            "flips": int(flips.sum()), "bitwise_identical_to_plain": bool(same)}
+            "flips": int(flips.sum()), "bitwise_identical_to_plain": bool(same),
+            "autotune": {"sample_steps": args.tune_steps, "seconds": t_tune, "shapes": shapes}}
 
 
 def bench_served(args, asi, workloads, torch):
@@ -288,6 +301,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--count", type=int, default=256, help="batched: instances")
     ap.add_argument("--batch-mode", default="fused", choices=["lockstep", "graph", "fused"])
+    ap.add_argument("--tune-steps", type=int, default=20,
+                    help="batched: autotune each instance on this many steps (0: off)")
     ap.add_argument("--jobs", type=int, default=2000, help="served: jobs")
     ap.add_argument("--plain-sample", type=int, default=64, help="served: jobs re-run alone")
     ap.add_argument("--rate", type=float, default=50.0, help="served: arrivals per second")

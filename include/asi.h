@@ -163,6 +163,35 @@ typedef struct {
 asi_status asi_set_timing(asi_handle h, int32_t enable);
 asi_status asi_get_timing(asi_handle h, asi_timing* out);
 
+/* Launch shapes of the relax (Sec. II.H); any valid choice gives the same
+ * flips, log and fields, bit for bit -- only the speed differs. */
+typedef struct {
+  int32_t relax_waves;  /* wavefronts per relax workgroup, 1..16 (the
+                           speculative path needs 16)                       */
+  int32_t l1_shift;     /* log2 of the relax tree's first-level tile, from
+                           the handle's minimum (tiles <= 2048) up to 20     */
+  int64_t spec_min;     /* flippable magnets at a step's start for the
+                           speculative path, >= 1 (it also needs a degree
+                           <= 128)                                           */
+  double default_ms;    /* asi_tune: sample time with the shapes it found    */
+  double tuned_ms;      /* asi_tune: sample time with the shapes it chose    */
+  int32_t trials;       /* asi_tune: shapes timed                            */
+  int32_t pad;
+} asi_tuning;
+/* Autotuner: times the next sample_steps (>= 1, clipped to the protocol)
+ * field steps under candidate shapes (speculation threshold, then tile
+ * size, then workgroup size), each run from a device snapshot of the
+ * handle's state, and keeps the fastest.  Every trial must reproduce the
+ * first trial's flip count and hash, else ASI_ESTATE.  The state, cursor
+ * and flip log are restored exactly; out (may be NULL) receives the choice.
+ * The snapshot is allocated through the handle's device allocator.
+ * ASI_ESTATE without a protocol, ASI_EINVAL if no step is left to sample. */
+asi_status asi_tune(asi_handle h, int64_t sample_steps, asi_tuning* out);
+/* Current shapes (the *_ms and trials fields are 0). */
+asi_status asi_get_tuning(asi_handle h, asi_tuning* out);
+/* Set shapes, e.g. from an earlier asi_tune; ASI_EINVAL if out of range. */
+asi_status asi_set_tuning(asi_handle h, const asi_tuning* t);
+
 asi_status asi_destroy(asi_handle h);
 
 /* Thread-local description of the last failure; valid until the next call

@@ -67,6 +67,12 @@ class AsiTiming(C.Structure):
                 ("relax_launches", C.c_int64), ("relax_ms", C.c_double)]
 
 
+class AsiTuning(C.Structure):
+    _fields_ = [("relax_waves", C.c_int32), ("l1_shift", C.c_int32), ("spec_min", C.c_int64),
+                ("default_ms", C.c_double), ("tuned_ms", C.c_double), ("trials", C.c_int32),
+                ("pad", C.c_int32)]
+
+
 class AsiServerStats(C.Structure):
     _fields_ = [("bursts", C.c_int64), ("admitted", C.c_int64), ("retired", C.c_int64),
                 ("pauses", C.c_int64), ("admit_s", C.c_double), ("wait_s", C.c_double),
@@ -99,6 +105,9 @@ SIGNATURES = {
     "asi_server_take": [P, C.c_int64, P, I64P, C.POINTER(C.c_uint64),
                         C.POINTER(C.c_double), C.POINTER(C.c_double)],
     "asi_server_get_stats": [P, C.POINTER(AsiServerStats)],
+    "asi_tune": [P, C.c_int64, C.POINTER(AsiTuning)],
+    "asi_get_tuning": [P, C.POINTER(AsiTuning)],
+    "asi_set_tuning": [P, C.POINTER(AsiTuning)],
     "asi_server_destroy": [P],
 }
 
@@ -308,6 +317,22 @@ class Sim:
                     relax_waves=i.relax_waves, device_bytes=i.device_bytes,
                     field_pass_bytes=i.field_pass_bytes,
                     flip_log_capacity=i.flip_log_capacity)
+
+    def tune(self, sample_steps: int = 20) -> dict:
+        """Autotune the relax launch shapes on the next sample_steps steps;
+        the state is left exactly as it was."""
+        t = AsiTuning()
+        _check(library().asi_tune(self.handle, int(sample_steps), C.byref(t)))
+        return {name: getattr(t, name) for name, _ in AsiTuning._fields_ if name != "pad"}
+
+    def tuning(self) -> dict:
+        t = AsiTuning()
+        _check(library().asi_get_tuning(self.handle, C.byref(t)))
+        return {name: getattr(t, name) for name in ("relax_waves", "l1_shift", "spec_min")}
+
+    def set_tuning(self, relax_waves: int, l1_shift: int, spec_min: int):
+        t = AsiTuning(relax_waves=int(relax_waves), l1_shift=int(l1_shift), spec_min=int(spec_min))
+        _check(library().asi_set_tuning(self.handle, C.byref(t)))
 
     def set_timing(self, on: bool = True):
         _check(library().asi_set_timing(self.handle, 1 if on else 0))

@@ -18,6 +18,9 @@ constexpr int kMaxL1Tiles = 2048;
 constexpr int kL2Group = 64;
 // Largest relax workgroup.
 constexpr int kMaxRelaxWaves = 16;
+// Above this degree a speculative batch holds too few members to beat the
+// max tree, so the relax never speculates.
+constexpr int kSpecMaxD = 128;
 
 // How the dipolar sum of a row is obtained at the start of a field step.
 enum FieldMode : int32_t {

@@ -553,8 +553,6 @@ constexpr int kWin = 2048;        // hot window entries
 constexpr int kHash = 4096;       // conflict table slots
 constexpr int kMaxPairs = 2048;   // member + neighbour slots per batch
 constexpr int kMaxMembers = 64;
-// Above this degree a batch holds too few members to beat the max tree.
-constexpr int kSpecMaxD = 128;
 // A step whose first kSwitchBatches batches commit fewer than spec_switch
 // (2.5 unless overridden) flips each on average -- an avalanche: every flip
 // makes a neighbour the next candidate -- continues on the max tree, which

@@ -569,6 +569,186 @@ asi_status asi_run(asi_handle h, int64_t t_begin, int64_t t_end, int64_t* flips_
   return run_steps(h, t_begin, t_end, flips_out);
 }
 
+static bool tuning_valid(const asi_sim* h, const asi_tuning* t) {
+  return t->relax_waves >= 1 && t->relax_waves <= kMaxRelaxWaves &&
+         t->l1_shift >= relax_l1_shift(h->n) && t->l1_shift <= 20 && t->spec_min >= 1;
+}
+
+static asi_status apply_tuning(asi_sim* h, const asi_tuning* t) {
+  h->relax_waves = t->relax_waves;
+  h->l1s = t->l1_shift;
+  h->hI.l1_shift = t->l1_shift;
+  h->hI.spec_min = t->spec_min;
+  h->lds = relax_lds_bytes(h->n, t->l1_shift);
+  return upload_desc(h);
+}
+
+asi_status asi_get_tuning(asi_handle h, asi_tuning* out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (!out) return fail(ASI_EINVAL, "out is NULL");
+  *out = asi_tuning{};
+  out->relax_waves = h->relax_waves;
+  out->l1_shift = h->l1s;
+  out->spec_min = h->hI.spec_min;
+  return ASI_OK;
+}
+
+asi_status asi_set_tuning(asi_handle h, const asi_tuning* t) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (!t) return fail(ASI_EINVAL, "tuning is NULL");
+  if (!tuning_valid(h, t)) return fail(ASI_EINVAL, "tuning out of range");
+  HIPCHK(hipStreamSynchronize(h->stream), h);
+  st = apply_tuning(h, t);
+  if (st != ASI_OK) return st;
+  return sync_and_check(h);
+}
+
+asi_status asi_tune(asi_handle h, int64_t sample_steps, asi_tuning* out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (h->K <= 0) return fail(ASI_ESTATE, "no field protocol set");
+  const int64_t t0 = h->cur_step + 1;
+  if (t0 >= h->K) return fail(ASI_EINVAL, "no protocol step left to sample");
+  const int64_t t1 = std::min(h->K, t0 + std::max<int64_t>(sample_steps, 1));
+  const int64_t n = h->n, nsl = (n + kSlice - 1) / kSlice;
+  InstDev& I = h->hI;
+  // the mutable state a step reads or writes (the candidate pool is rebuilt
+  // by every field pass; flip-log entries past the cursor are rewritten by
+  // the real run)
+  struct Arr {
+    void* p;
+    size_t bytes;
+    void* snap;
+  };
+  std::vector<Arr> arrs = {{I.s, (size_t)n, nullptr},          {I.dirty, (size_t)n, nullptr},
+                           {I.hd_par, 8 * (size_t)n, nullptr},  {I.hd_perp, 8 * (size_t)n, nullptr},
+                           {I.h_par, 8 * (size_t)n, nullptr},   {I.h_perp, 8 * (size_t)n, nullptr},
+                           {I.key, 8 * (size_t)n, nullptr},     {I.ver, 4 * (size_t)n, nullptr},
+                           {I.t1key, 8 * (size_t)nsl, nullptr}, {I.t1idx, 4 * (size_t)nsl, nullptr},
+                           {I.step_flips + t0, 4 * (size_t)(t1 - t0), nullptr}};
+  // trials are not charged to the handle's kernel timing
+  st = sync_and_check(h);
+  if (st != ASI_OK) return st;
+  const bool timing0 = h->timing;
+  h->timing = false;
+  auto release = [&]() {
+    for (auto& a : arrs)
+      if (a.snap) h->mem.release(a.snap);
+  };
+  for (auto& a : arrs) {
+    a.snap = h->mem.alloc(a.bytes);
+    if (!a.snap) {
+      release();
+      h->timing = timing0;
+      return fail(ASI_ENOMEM, "device allocation failed (tuning snapshot)");
+    }
+    HIPCHK(hipMemcpyAsync(a.snap, a.p, a.bytes, hipMemcpyDeviceToDevice, h->stream), h);
+  }
+  RunDev r0{};
+  st = read_run(h, &r0);
+  if (st != ASI_OK) {
+    release();
+    h->timing = timing0;
+    return st;
+  }
+  const int64_t step0 = h->cur_step;
+  auto restore = [&]() -> asi_status {
+    for (auto& a : arrs)
+      HIPCHK(hipMemcpyAsync(a.p, a.snap, a.bytes, hipMemcpyDeviceToDevice, h->stream), h);
+    HIPCHK(hipMemcpyAsync(h->dR, &r0, sizeof(RunDev), hipMemcpyHostToDevice, h->stream), h);
+    h->cur_step = step0;
+    return sync_and_check(h);
+  };
+  asi_tuning cur{};
+  (void)asi_get_tuning(h, &cur);
+  const asi_tuning first = cur;
+  bool have_ref = false;
+  int64_t ref_flips = 0;
+  uint64_t ref_hash = 0;
+  int32_t trials = 0;
+  // one timed sample under shapes c; every sample must match the first
+  auto trial = [&](const asi_tuning& c, double& ms) -> asi_status {
+    asi_status e = restore();
+    if (e == ASI_OK) e = apply_tuning(h, &c);
+    if (e == ASI_OK) e = sync_and_check(h);
+    if (e != ASI_OK) return e;
+    const double ta = now_s();
+    int64_t f = 0;
+    e = run_steps(h, t0, t1, &f);
+    ms = (now_s() - ta) * 1e3;
+    if (e != ASI_OK) return e;
+    RunDev r{};
+    e = read_run(h, &r);
+    if (e != ASI_OK) return e;
+    ++trials;
+    if (!have_ref) {
+      have_ref = true;
+      ref_flips = r.flips;
+      ref_hash = r.hash;
+    } else if (r.flips != ref_flips || r.hash != ref_hash) {
+      return fail(ASI_ESTATE, "launch shapes changed the flips (tuning aborted)");
+    }
+    return ASI_OK;
+  };
+  double best_ms = 0.0;
+  st = trial(cur, best_ms);
+  const double default_ms = best_ms;
+  asi_tuning best = cur;
+  auto consider = [&](asi_tuning c) -> asi_status {
+    if (!tuning_valid(h, &c)) return ASI_OK;
+    double ms = 0.0;
+    asi_status e = trial(c, ms);
+    if (e != ASI_OK) return e;
+    if (ms < 0.97 * best_ms) {  // a clear win only
+      best_ms = ms;
+      best = c;
+    }
+    return ASI_OK;
+  };
+  // 1. speculation threshold (only where the degree allows speculation)
+  if (st == ASI_OK && h->D <= kSpecMaxD && cur.relax_waves == kMaxRelaxWaves) {
+    const int64_t mins[] = {8, 256, INT64_MAX};
+    for (int64_t m : mins) {
+      if (st != ASI_OK || m == cur.spec_min) continue;
+      asi_tuning c = best;
+      c.spec_min = m;
+      st = consider(c);
+    }
+  }
+  // 2. first-level tile of the max tree
+  for (int dl = 1; st == ASI_OK && dl <= 2; ++dl) {
+    asi_tuning c = best;
+    c.l1_shift = cur.l1_shift + dl;
+    st = consider(c);
+  }
+  // 3. workgroup size, where the relax does not speculate
+  if (st == ASI_OK && (h->D > kSpecMaxD || best.spec_min == INT64_MAX)) {
+    const int32_t ws[] = {8, 4};
+    for (int32_t w : ws) {
+      if (st != ASI_OK) break;
+      asi_tuning c = best;
+      c.relax_waves = w;
+      st = consider(c);
+    }
+  }
+  asi_status st2 = restore();
+  if (st2 == ASI_OK) st2 = apply_tuning(h, st == ASI_OK ? &best : &first);
+  if (st2 == ASI_OK) st2 = sync_and_check(h);
+  release();
+  h->timing = timing0;
+  if (st != ASI_OK) return st;
+  if (st2 != ASI_OK) return st2;
+  if (out) {
+    *out = best;
+    out->default_ms = default_ms;
+    out->tuned_ms = best_ms;
+    out->trials = trials;
+  }
+  return ASI_OK;
+}
+
 asi_status asi_compute_fields(asi_handle h, int64_t t) {
   asi_status st = check_handle(h);
   if (st != ASI_OK) return st;

@@ -31,6 +31,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(asi.AsiDevice) == 4 * 8
     assert C.sizeof(asi.AsiInfo) == 8 + 8 + 4 + 4 + 8 + 8 + 8
     assert C.sizeof(asi.AsiServerStats) == 4 * 8 + 4 * 8
+    assert C.sizeof(asi.AsiTuning) == 4 + 4 + 8 + 8 + 8 + 4 + 4
 
 
 def test_invalid_arguments_fail_before_touching_the_device():
@@ -51,6 +52,9 @@ def test_invalid_arguments_fail_before_touching_the_device():
     assert lib.asi_destroy(None) == asi.ASI_OK
     assert lib.asi_batch_run(None, 0, 0, None) == asi.ASI_EINVAL
     assert lib.asi_server_get_stats(None, None) == asi.ASI_EINVAL
+    assert lib.asi_tune(None, 10, None) == asi.ASI_EINVAL
+    assert lib.asi_get_tuning(None, None) == asi.ASI_EINVAL
+    assert lib.asi_set_tuning(None, None) == asi.ASI_EINVAL
     assert lib.asi_server_step(None, 1.0, None) == asi.ASI_EINVAL
     assert lib.asi_server_destroy(None) == asi.ASI_OK
 

@@ -261,6 +261,62 @@ def test_served_equals_plain_bitwise(budget_ms, big, slots, count, monkeypatch):
     srv.close()
 
 
+# ------------------------------------------------------------------ autotuner
+@pytest.mark.parametrize("family,d,thermal", [("kagome", 3, 0.005), ("pinwheel", 8, 0.0),
+                                              ("square", 4, 0.003)])
+def test_tune_restores_state_and_keeps_results(family, d, thermal):
+    H = W.rotating(120, 0.08, 60) if family == "kagome" else W.linear_ramp(120, 0.3, -0.3, 20.0)
+    w = W.family_instance(family, 20000, d, seed=7, H=H, thermal_std=thermal, thermal_seed=3)
+    say("tune", family, w.n, d, thermal)
+    ref = gpu_sim(w)
+    ref.run()
+    lr, sr = ref.flip_log(cap=0), ref.state()[0]
+    s = gpu_sim(w)
+    s.run(0, 40)
+    s0, hp0, hq0, st0 = s.state()
+    l0 = s.flip_log(cap=0)
+    res = s.tune(sample_steps=30)
+    say("tuning", res)
+    assert res["trials"] >= 3 and res["tuned_ms"] <= res["default_ms"]
+    # state, cursor and log exactly as before
+    s1, hp1, hq1, st1 = s.state()
+    l1 = s.flip_log(cap=0)
+    assert np.array_equal(s0, s1) and np.array_equal(hp0, hp1) and np.array_equal(hq0, hq1)
+    assert st0 == st1 and (l0["count"], l0["hash"]) == (l1["count"], l1["hash"])
+    # the tuned shapes finish the run with the untuned run's flips
+    s.run(40, w.n_steps)
+    l2 = s.flip_log(cap=0)
+    assert (l2["count"], l2["hash"]) == (lr["count"], lr["hash"])
+    assert np.array_equal(s.state()[0], sr)
+    # explicit shapes: out-of-range values are refused, valid ones change nothing
+    t = s.tuning()
+    with pytest.raises(asi.AsiError):
+        s.set_tuning(0, t["l1_shift"], 1)
+    with pytest.raises(asi.AsiError):
+        s.set_tuning(16, 5, 1)   # tiles hold at least 64 magnets
+    s3 = gpu_sim(w)
+    s3.set_tuning(4, t["l1_shift"] + 1, 2 ** 62)
+    s3.run()
+    l3 = s3.flip_log(cap=0)
+    assert (l3["count"], l3["hash"]) == (lr["count"], lr["hash"])
+
+
+def test_tuned_instances_batch_bitwise():
+    ws = W.batched_sweep(count=6, seed=4, n_steps=60)
+    sims, refs = [], []
+    for w in ws:
+        r = gpu_sim(w)
+        r.run()
+        refs.append(r.flip_log(cap=0))
+        s = gpu_sim(w)
+        s.tune(sample_steps=15)
+        sims.append(s)
+    asi.batch_run(sims, mode="fused")
+    for s, r in zip(sims, refs):
+        lg = s.flip_log(cap=0)
+        assert (lg["count"], lg["hash"]) == (r["count"], r["hash"])
+
+
 # ------------------------------------------------------------------ edge cases
 def test_single_magnet_and_no_neighbours():
     say("single magnet")
