@@ -37,12 +37,16 @@ PROFILE = os.path.join(ROOT, "profiles", "k_field_kagome577_rotating.md")
 
 
 def field_pass_digest():
-    """SHA-256 of the kernel source the full-field pass is built from."""
-    txt = open(os.path.join(ROOT, "paper_2002_11401_amd", "csrc", "asi_kernels.hip")).read()
+    """SHA-256 of the kernel source the full-field pass is built from: the
+    device data layout header, then the kernel file's common part and its
+    field-phase section."""
+    csrc = os.path.join(ROOT, "paper_2002_11401_amd", "csrc")
+    hdr = open(os.path.join(csrc, "asi_internal.h")).read()
+    txt = open(os.path.join(csrc, "asi_kernels.hip")).read()
     a = txt.index("// ------------------------------------------------------------ neighbours")
     b = txt.index("// ------------------------------------------------------------ field phase")
     c = txt.index("// ------------------------------------------------------------ relax")
-    return hashlib.sha256((txt[:a] + txt[b:c]).encode()).hexdigest()
+    return hashlib.sha256((hdr + txt[:a] + txt[b:c]).encode()).hexdigest()
 
 
 def recorded_traffic():
