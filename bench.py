@@ -31,6 +31,8 @@ HBM_PEAK_GBS = 8000.0
 def progress(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 METRIC = "neighbour interactions/s & flips/s; batched/served runs/s + p99 vs plain"
+# degree from which a full-field pass runs one workgroup per 64-row slice
+HD_MIN_DEGREE = 128
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_field_kagome577_rotating.md")
@@ -139,7 +141,9 @@ def bench_plain(args, asi, workloads, torch):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": recorded_traffic() if w.name == "kagome577_rotating" else None,
-                     "kernel": "k_field (full-field pass)"},
+                     "kernel": ("k_field_hd (full-field pass, a workgroup per 64-row slice)"
+                                if info["max_degree"] >= HD_MIN_DEGREE
+                                else "k_field (full-field pass, a lane per row)")},
         "paper_context": {"field_calcs_per_s": 1e8, "hardware": "NVIDIA Tesla V100 32GB",
                           "workload": "square ASI, 8-spin neighbourhood, saturated size"},
     }

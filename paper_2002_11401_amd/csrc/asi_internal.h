@@ -114,6 +114,11 @@ void launch_neighbour_fill(const double* x, const double* y, const double* mx, c
                            const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,
                            double cut2, double alpha, int32_t D, int32_t* col, double* A,
                            double* B, int32_t* rcol, double* rA, double* rBr, hipStream_t st);
+// Degree from which a single instance's full-field pass (every row
+// gathered) uses one workgroup per 64-row slice instead of one lane per row.
+constexpr int kHdMinD = 128;
+// Full-field pass of one instance of degree >= kHdMinD (field_mode full).
+void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, hipStream_t st);
 // Grid-wide field pass for every active instance of the table; rebuilds the
 // relax structures of every paused one.
 void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,

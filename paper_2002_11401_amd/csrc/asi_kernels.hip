@@ -288,6 +288,9 @@ __global__ void k_nb_fill(const double* __restrict__ x, const double* __restrict
 // row's total field and key and returns (key, index | sign bit).  Every
 // field pass (grid-wide or inside a fused workgroup) calls this one
 // function, so they agree bit for bit.
+__device__ __forceinline__ double field_finish(const InstDev* __restrict__ I, int64_t i, int64_t t,
+                                               double p, double pq, uint32_t& payload);
+
 __device__ __forceinline__ double field_row(const InstDev* __restrict__ I, int64_t i, int64_t t,
                                    uint32_t& payload) {
   const int8_t* __restrict__ s = I->s;
@@ -339,6 +342,14 @@ __device__ __forceinline__ double field_row(const InstDev* __restrict__ I, int64
     p = I->hd_par[i];
     pq = I->hd_perp[i];
   }
+  return field_finish(I, i, t, p, pq, payload);
+}
+
+// Eq. 2 for row i from its dipolar sums (p, pq): plus H[t] and the thermal
+// draw, projected; writes the total field and the key, returns the key.
+__device__ __forceinline__ double field_finish(const InstDev* __restrict__ I, int64_t i, int64_t t,
+                                               double p, double pq, uint32_t& payload) {
+  const int8_t* __restrict__ s = I->s;
   const double mxi = I->mx[i], myi = I->my[i];
   double hp = p, hq = pq;
   if (t >= 0) {
@@ -455,6 +466,95 @@ __global__ __launch_bounds__(kFieldBlock) void k_field(const InstDev* __restrict
   }
   __syncthreads();
   if (bal) pool_put(I, key, payload, bal, (int64_t)bbase + wcount[wave]);
+}
+
+// Full-field pass for an instance of high degree (every row gathered): one
+// workgroup of kHdThreads per 64-row slice.  The slice's tables are one
+// contiguous block (slot k of its rows at k * 64 + lane); the workgroup
+// reads them in chunks of kHdChunk slots, four entries per thread with the
+// next chunk's columns prefetched, so a chunk costs one round trip for the
+// whole block instead of one per eight slots per row, and stages each slot's
+// signed couplings in LDS.  The lane of each row then adds its chunk in
+// ascending slot order: the same sums, in the same order, as field_row.
+constexpr int kHdChunk = 64;
+constexpr int kHdThreads = 512;
+constexpr int kHdPer = kHdChunk * 64 / kHdThreads;  // entries per thread per chunk
+
+__global__ __launch_bounds__(kHdThreads) void k_field_hd(const InstDev* __restrict__ insts,
+                                                   RunDev* __restrict__ runs) {
+  __shared__ double sa[kHdChunk * 64];
+  __shared__ double sb[kHdChunk * 64];
+  const RunDev* R = runs;
+  if (!R->active) return;
+  const InstDev* I = insts;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int32_t D = I->D;
+  const int64_t base = slot_of(row0, D, 0);  // start of the slice's block
+  const int8_t* __restrict__ s = I->s;
+  const int64_t i = row0 + lane;
+  const bool own = tid < 64 && i < I->n;   // wavefront 0 owns the rows
+  const int32_t L = own ? I->len[i] : 0;
+  double p = 0.0, pq = 0.0;
+  int32_t jc[kHdPer];
+#pragma unroll
+  for (int q = 0; q < kHdPer; ++q) {
+    const int e = tid + q * kHdThreads;
+    jc[q] = (e / 64 < D) ? __builtin_nontemporal_load(&I->col[base + e]) : -1;
+  }
+  for (int32_t k0 = 0; k0 < D; k0 += kHdChunk) {
+    double a[kHdPer], b[kHdPer];
+    int sg[kHdPer];
+#pragma unroll
+    for (int q = 0; q < kHdPer; ++q) {
+      const int e = tid + q * kHdThreads;
+      const bool ok = k0 + e / 64 < D;
+      const int64_t sl = base + (int64_t)k0 * 64 + e;
+      a[q] = ok ? __builtin_nontemporal_load(&I->A[sl]) : 0.0;
+      b[q] = ok ? __builtin_nontemporal_load(&I->B[sl]) : 0.0;
+      sg[q] = (ok && jc[q] >= 0) ? s[jc[q]] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kHdPer; ++q) {
+      const int e = tid + q * kHdThreads;
+      const bool ok = k0 + kHdChunk + e / 64 < D;
+      jc[q] = ok ? __builtin_nontemporal_load(&I->col[base + (int64_t)(k0 + kHdChunk) * 64 + e])
+                 : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kHdPer; ++q) {
+      const int e = tid + q * kHdThreads;
+      sa[e] = (sg[q] > 0) ? a[q] : -a[q];
+      sb[e] = (sg[q] > 0) ? b[q] : -b[q];
+    }
+    __syncthreads();
+    if (own) {
+      const int kn = L - k0 < kHdChunk ? L - k0 : kHdChunk;
+      for (int kk = 0; kk < kn; ++kk) {
+        p += sa[kk * 64 + lane];
+        pq += sb[kk * 64 + lane];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid >= 64) return;
+  uint32_t payload = 0;
+  double key = 0.0;
+  if (own) key = field_finish(I, i, R->t, p, pq, payload);
+  double mk = key;
+  uint32_t mp = payload;
+  wave_argmax(mk, mp);
+  if (lane == 0) {
+    I->t1key[row0 >> 6] = mk;
+    I->t1idx[row0 >> 6] = mp;
+  }
+  const unsigned long long bal = __ballot(key > 0.0);
+  if (bal) {
+    int pbase = 0;
+    if (lane == 0) pbase = atomicAdd(I->ccount, __popcll(bal));
+    pbase = __builtin_amdgcn_readfirstlane(pbase);
+    pool_put(I, key, payload, bal, pbase);
+  }
 }
 
 // ------------------------------------------------------------ relax
@@ -1640,6 +1740,12 @@ void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,
   if (nblocks <= 0) return;
   hipLaunchKernelGGL(k_field, dim3((unsigned)nblocks), dim3(kFieldBlock), 0, st, insts, runs,
                      blk_inst, blk_row0);
+}
+
+void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_field_hd, dim3((unsigned)((n + 63) / 64)), dim3(kHdThreads), 0, st, inst,
+                     run);
 }
 
 void launch_relax(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,

@@ -144,7 +144,10 @@ void field_pass(asi_sim* s) {
     tp.kind = 0;
     (void)hipEventRecord(tp.a, s->stream);
   }
-  launch_field(s->dI, s->dR, s->blk_inst, s->blk_row0, s->nblocks, s->stream);
+  if (s->hI.field_mode == kFieldFull && s->D >= kHdMinD)
+    launch_field_hd(s->dI, s->dR, s->n, s->stream);
+  else
+    launch_field(s->dI, s->dR, s->blk_inst, s->blk_row0, s->nblocks, s->stream);
   if (s->timing) {
     (void)hipEventRecord(tp.b, s->stream);
     s->timers.push_back(tp);

@@ -391,6 +391,39 @@ def test_full_pass_and_dirty_row_modes_bitwise():  # noqa: D103
     assert_same_flips(lb, r, b.state()[0], o.spins())
 
 
+@pytest.mark.parametrize("side,d", [(40, 10.0), (23, 7.0)])
+def test_high_degree_full_pass_bitwise(side, d):
+    """At 128 or more neighbours the full-field pass runs one workgroup per
+    64-row slice; its sums must equal the one-lane-per-row gather bit for bit
+    (dirty mode gathers every row at the first step and the rows next to
+    flips later), and the flips must match the oracle."""
+    xy, theta = W.pinwheel_diamond(side)
+    n = len(theta)
+    H = W.linear_ramp(80, 0.1, -0.1, 30.0)
+    w = W.Workload(f"pinwheel{side}", xy, theta, W.polarised_spins(theta, H[0]),
+                   W.disorder_hk(n, 0.2, 0.05, 11), H, alpha=0.0013, neighbor_distance=d,
+                   b=0.38, c=1, beta=1.5, gamma=3.9, thermal_std=0.002, thermal_seed=6)
+    a = gpu_sim(w, field_mode="full")
+    b = gpu_sim(w, field_mode="dirty")
+    say("high-degree full pass", n, a.info()["max_degree"])
+    assert a.info()["max_degree"] >= 128
+    for t in range(-1, 80, 20):
+        a.compute_fields(t)
+        b.compute_fields(t)
+        for x, y in zip(a.state()[:3], b.state()[:3]):
+            assert np.array_equal(x, y)
+    a.set_state(w.spin0, -1)
+    b.set_state(w.spin0, -1)
+    a.run()
+    b.run()
+    la, lb = a.flip_log(), b.flip_log()
+    assert la["hash"] == lb["hash"] and la["count"] == lb["count"] > 0
+    for x, y in zip(a.state()[:3], b.state()[:3]):
+        assert np.array_equal(x, y)
+    o, r = oracle_run(w)
+    assert_same_flips(la, r, a.state()[0], o.spins())
+
+
 @pytest.mark.parametrize("mode", ["carry", "dirty"])
 def test_fused_batch_thermal_bitwise_and_oracle(mode):
     """Fused persistent batch (each instance's workgroup runs its own field
