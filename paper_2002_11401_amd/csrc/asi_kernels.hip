@@ -625,6 +625,8 @@ struct RelaxShared {
   int pause;  // the relax stops here and resumes in a later launch
   double key;
   uint32_t pay;
+  // predicted next flip: high 32 bits of the best updated key, then its index
+  unsigned long long pfk;
 };
 
 // True once the deadline (device constant-rate clock; 0: none) has passed.
@@ -1350,6 +1352,7 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
     sh.n1 = 0;
     sh.n2 = 0;
     sh.nr = 0;
+    sh.pfk = 0ull;
   }
   __syncthreads();
   for (int g = wave; g < nt2; g += NW) {
@@ -1368,6 +1371,12 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
   int status = 0;
   const int per2 = (nt2 + 63) >> 6;
   const int64_t flips0 = flips;
+  // Row of the predicted next flip (the best magnet the last update pushed
+  // over the astroid, the usual next flip of an avalanche), loaded while the
+  // tree is brought up to date; used when the prediction holds.
+  int64_t pf_j = -1;
+  int32_t pf_c[2] = {-1, -1};
+  double pf_a[2] = {0.0, 0.0}, pf_b[2] = {0.0, 0.0};
 
   while (true) {
     if (wave == 0) {
@@ -1426,15 +1435,20 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
     // atomics (positive doubles order like their bit patterns), then the
     // lowest index among the updates holding it.
     const bool incr = D <= 2 * NT;
+    const bool hit = j == pf_j;
     int u_i[2], u_e[2], u_s[2];
     double u_k[2];
+    double tb_k = 0.0;  // this thread's best updated key, for the prediction
+    uint32_t tb_i = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) u_i[h] = -1;
     for (int k = tid, h = 0; k < D; k += NT, ++h) {
       const int64_t sl = j * D + k;
-      const int32_t i = colp[sl];
+      const bool pre = hit && h < 2;
+      const int32_t i = pre ? pf_c[h & 1] : colp[sl];
       if (i >= 0) {
-        const double da = two * Ap[sl], db = two * Brp[sl];
+        const double da = two * (pre ? pf_a[h & 1] : Ap[sl]);
+        const double db = two * (pre ? pf_b[h & 1] : Brp[sl]);
         const double hp = hpp[i] + da;
         const double hq = hqp[i] + db;
         if (mode == kFieldCarry) {
@@ -1453,6 +1467,10 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
         if (!incr || (L.l1k[e] > 0.0 && (L.l1i[e] & 0x7fffffffu) == (uint32_t)i))
           L.l1resc[e] = 1;
         if (kk > 0.0) atomicMax(&L.l1nk[e], (unsigned long long)__double_as_longlong(kk));
+        if (kk > tb_k) {
+          tb_k = kk;
+          tb_i = (uint32_t)i;
+        }
         if (h < 2) {
           u_i[h] = i;
           u_e[h] = e;
@@ -1461,7 +1479,27 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
         }
       }
     }
+    wave_argmax(tb_k, tb_i);
+    if (lane == 0 && tb_k > 0.0)
+      atomicMax(&sh.pfk, ((unsigned long long)__double_as_longlong(tb_k) & 0xffffffff00000000ull) |
+                             (unsigned long long)tb_i);
     __syncthreads();
+    {
+      const unsigned long long pk = sh.pfk;
+      pf_j = pk ? (int64_t)(pk & 0xffffffffull) : -1;
+      if (pf_j >= 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = tid + h * NT;
+          if (k < D) {
+            const int64_t sl = pf_j * D + k;
+            pf_c[h] = colp[sl];
+            pf_a[h] = Ap[sl];
+            pf_b[h] = Brp[sl];
+          }
+        }
+      }
+    }
     if (incr) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -1471,6 +1509,7 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
       }
     }
     __syncthreads();
+    if (tid == 0) sh.pfk = 0ull;  // every thread has read it
     const int n1 = sh.n1;
     for (int u = tid; u < n1; u += NT) {
       const int e = L.l1list[u];
