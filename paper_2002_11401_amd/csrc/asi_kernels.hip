@@ -735,6 +735,10 @@ struct SpecShared {
   uint32_t cmp, cmv;
   double rk;        // best entry a merge discarded into the pool
   uint32_t rp, rv;
+  double tau;       // refill threshold (selective refill)
+  int over;         // selective refill: more entries above tau than fit
+  double wk[16];    // per-wavefront best entries (selective refill)
+  uint32_t wp[16], wv[16];
 };
 
 // Block-wide bitonic sort, best first, of P (a power of two) entries.
@@ -934,6 +938,129 @@ __device__ __forceinline__ void refill(const InstDev* I, const SpecLds& S, SpecS
   __syncthreads();
 }
 
+// Refill for a large pool: a threshold tau from a sorted sample of the
+// pool's keys puts about kWin / 2 entries above it; one pass drops stale
+// entries, sends the current ones above tau to staging and those at or
+// below tau to the other pool buffer, keeping the best of those (pool
+// order) as the cold bound; staging is sorted and merged into the window,
+// whose overflow joins the pool and the bound, which stays exact.  Only
+// about kWin entries are sorted instead of the whole pool.  If more current
+// entries than staging holds lie above tau, the pass is discarded and the
+// full refill runs instead.
+__device__ __forceinline__ void refill_select(const InstDev* I, const SpecLds& S, SpecShared& sh) {
+  const int tid = threadIdx.x, NT = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  const int cb = sh.cb;
+  const int64_t ncold = sh.ncold;
+  for (int q = tid; q < kWin; q += NT) {
+    S.sk[q] = I->ckey[cb][(int64_t)q * ncold / kWin];
+    S.sp[q] = (uint32_t)q;
+    S.sv[q] = 0u;
+  }
+  __syncthreads();
+  bitonic_best_first(S.sk, S.sp, S.sv, kWin);
+  if (tid == 0) {
+    int r = (int)((int64_t)(kWin / 2) * kWin / ncold);
+    if (r < 1) r = 1;
+    sh.tau = S.sk[r];
+    sh.ns = 0;
+    sh.over = 0;
+    sh.ncold_out = 0;
+    sh.rk = -1.0;
+    sh.rp = 0x7fffffffu;
+    sh.rv = 0u;
+  }
+  __syncthreads();
+  const double tau = sh.tau;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  double bk = -1.0;
+  uint32_t bp = 0x7fffffffu, bv = 0u;
+  for (int64_t q0 = 0; q0 < ncold; q0 += NT) {
+    const int64_t q = q0 + tid;
+    bool up = false, down = false;
+    double k = 0.0;
+    uint32_t pay = 0, ver = 0;
+    if (q < ncold) {
+      k = I->ckey[cb][q];
+      pay = I->cpay[cb][q];
+      ver = I->cver[cb][q];
+      const bool cur = I->ver[pay & 0x7fffffffu] == ver;
+      up = cur && k > tau;
+      down = cur && !(k > tau);
+    }
+    const unsigned long long bu = __ballot(up), bd = __ballot(down);
+    int ubase = 0, dbase = 0;
+    if (lane == 0) {
+      if (bu) ubase = atomicAdd(&sh.ns, __popcll(bu));
+      if (bd) dbase = (int)atomicAdd((unsigned long long*)&sh.ncold_out, (unsigned long long)__popcll(bd));
+    }
+    ubase = __builtin_amdgcn_readfirstlane(ubase);
+    dbase = __builtin_amdgcn_readfirstlane(dbase);
+    if (up) {
+      const int pos = ubase + __popcll(bu & lt);
+      if (pos < kWin) {
+        S.sk[pos] = k;
+        S.sp[pos] = pay;
+        S.sv[pos] = ver;
+      } else {
+        sh.over = 1;
+      }
+    }
+    if (down) {
+      const int64_t pos = dbase + __popcll(bd & lt);
+      I->ckey[cb ^ 1][pos] = k;
+      I->cpay[cb ^ 1][pos] = pay;
+      I->cver[cb ^ 1][pos] = ver;
+      if (better_e(k, pay, ver, bk, bp, bv)) {
+        bk = k;
+        bp = pay;
+        bv = ver;
+      }
+    }
+  }
+  // best entry sent down: per wavefront, then over the wavefronts
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ok = __shfl_down(bk, off);
+    const uint32_t op = __shfl_down(bp, off), ov = __shfl_down(bv, off);
+    if (lane + off < 64 && better_e(ok, op, ov, bk, bp, bv)) {
+      bk = ok;
+      bp = op;
+      bv = ov;
+    }
+  }
+  if (lane == 0) {
+    sh.wk[wave] = bk;
+    sh.wp[wave] = bp;
+    sh.wv[wave] = bv;
+  }
+  __syncthreads();
+  if (sh.over) {  // too many above tau: the full refill, from the same pool
+    refill(I, S, sh);
+    return;
+  }
+  if (tid == 0) {
+    for (int w = 0; w < (NT >> 6); ++w)
+      if (better_e(sh.wk[w], sh.wp[w], sh.wv[w], sh.rk, sh.rp, sh.rv)) {
+        sh.rk = sh.wk[w];
+        sh.rp = sh.wp[w];
+        sh.rv = sh.wv[w];
+      }
+  }
+  __syncthreads();
+  const int ns = sh.ns;
+  sort_staging(S, ns);
+  const int nx = sh.nx;
+  const int keep = nx + ns < kWin ? nx + ns : kWin;
+  merge_keep(I, S, sh, 0, nx, ns, keep, cb ^ 1);
+  if (tid == 0) {
+    sh.cb = cb ^ 1;
+    sh.ncold = sh.ncold_out;
+    sh.cmk = sh.rk;
+    sh.cmp = sh.rp;
+    sh.cmv = sh.rv;
+  }
+  __syncthreads();
+}
+
 // Window entries better than cold_max (all of them when the pool is empty).
 __device__ __forceinline__ int count_safe(const SpecLds& S, const SpecShared& sh) {
   const int nx = sh.nx;
@@ -1001,7 +1128,10 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
     const int pause = sh.pause;
     if (sh.safe == 0 || sh.ncold + kMaxPairs + kWin > I->ccap) {
       if (sh.ncold == 0 && sh.safe == 0) break;
-      refill(I, S, sh);
+      if (sh.ncold > 4 * kWin)
+        refill_select(I, S, sh);
+      else
+        refill(I, S, sh);
       if (tid == 0) sh.safe = count_safe(S, sh);
       __syncthreads();
       if (sh.safe == 0) break;  // the pool held stale entries only
