@@ -61,10 +61,10 @@ struct InstDev {
   // mutable state
   int8_t* s;              // [n] spins
   uint8_t* dirty;         // [n] row's dipolar sum must be gathered at the next step
-  double* hd_par;         // [n] dipolar field (gathered, plus flip deltas)
-  double* hd_perp;
-  double* h_par;          // [n] total field (dipolar + applied + thermal)
-  double* h_perp;
+  // Field pairs (x: easy axis, y: hard axis) kept together, so the relax
+  // reads or writes a magnet's pair with one 16-byte access.
+  double2* hd;            // [n] dipolar field (gathered, plus flip deltas)
+  double2* h;             // [n] total field (dipolar + applied + thermal)
   double* key;            // [n] Eq. 5 LHS if flippable, else 0
   double* t1key;          // [ceil(n/64)] per-64-row maximum key
   uint32_t* t1idx;        //   its index, bit 31 set when that spin is -1

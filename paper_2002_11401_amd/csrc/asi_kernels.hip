@@ -333,14 +333,14 @@ __device__ __forceinline__ double field_row(const InstDev* __restrict__ I, int64
       }
     }
     if (mode != kFieldFull) {
-      I->hd_par[i] = p;
-      I->hd_perp[i] = pq;
+      I->hd[i] = make_double2(p, pq);
       I->dirty[i] = 0;
     }
   } else {
     // carried, or no neighbour flipped since the last gather
-    p = I->hd_par[i];
-    pq = I->hd_perp[i];
+    const double2 c = I->hd[i];
+    p = c.x;
+    pq = c.y;
   }
   return field_finish(I, i, t, p, pq, payload);
 }
@@ -364,8 +364,7 @@ __device__ __forceinline__ double field_finish(const InstDev* __restrict__ I, in
       hq = hq + (ty * mxi - tx * myi);
     }
   }
-  I->h_par[i] = hp;
-  I->h_perp[i] = hq;
+  I->h[i] = make_double2(hp, hq);
   const int si = s[i];
   const double key = switching_key(si, hp, hq, I->hk[i], I->b, I->c, I->e_par, I->e_perp);
   I->key[i] = key;
@@ -1079,8 +1078,8 @@ __device__ __forceinline__ int count_safe(const SpecLds& S, const SpecShared& sh
 __device__ inline uint32_t hash_slot(uint32_t i) { return (i * 2654435761u) >> (32 - 12); }
 
 // Relax at step t in speculative batches (needs 1024 threads).  flips,
-// logpos and hash are the running counters (logpos and hash significant in
-// thread 0).  Returns 0, -5 (flip cap reached with a flippable magnet left),
+// logpos and hash are the running counters (hash significant in thread 0).
+// Returns 0, -5 (flip cap reached with a flippable magnet left),
 // 1 (deadline passed after at least one batch, flippable magnets left) or
 // 2 (after kSwitchBatches batches the mean batch is below spec_switch flips:
 // the flippable magnets crowd each other's neighbourhoods, and the step
@@ -1251,11 +1250,13 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
         const uint32_t mpay = S.mp[pr_r[u]];
         const double two = (mpay & 0x80000000u) ? 2.0 : -2.0;  // s_new = -s_old
         const double da = two * pr_a[u], db = two * pr_b[u];
-        nh_p[u] = I->h_par[i] + da;
-        nh_q[u] = I->h_perp[i] + db;
+        const double2 hi = I->h[i];
+        nh_p[u] = hi.x + da;
+        nh_q[u] = hi.y + db;
         if (mode == kFieldCarry) {
-          nd_p[u] = I->hd_par[i] + da;
-          nd_q[u] = I->hd_perp[i] + db;
+          const double2 di = I->hd[i];
+          nd_p[u] = di.x + da;
+          nd_q[u] = di.y + db;
         }
         nsi[u] = I->s[i];
         nver[u] = I->ver[i];
@@ -1312,18 +1313,19 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
       I->key[j] = 0.0;
       I->ver[j] = xv[S.mpos[tid]] + 1u;
     }
-    if (tid == 0) {
+    if (tid < 64) {  // log the members in order (one lane each), then fold them into the hash
+      const uint32_t jr = (tid < p) ? (S.mp[tid] & 0x7fffffffu) : 0u;
+      if (tid < p && logpos + tid < I->log_cap) {
+        I->log_t[logpos + tid] = (int32_t)t;
+        I->log_j[logpos + tid] = (int32_t)jr;
+      }
       for (int r = 0; r < p; ++r) {
-        const uint32_t j = S.mp[r] & 0x7fffffffu;
-        if (logpos < I->log_cap) {
-          I->log_t[logpos] = (int32_t)t;
-          I->log_j[logpos] = (int32_t)j;
-        }
-        ++logpos;
-        const uint64_t w = ((uint64_t)(uint32_t)t << 32) | (uint64_t)j;
+        const uint64_t w = ((uint64_t)(uint32_t)t << 32) |
+                           (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)jr, r);
         hash = (hash ^ w) * 0x100000001b3ull;
       }
     }
+    logpos += p;
     const double cmk = sh.cmk;
     const uint32_t cmp = sh.cmp, cmv = sh.cmv;
     const int cb = sh.cb;
@@ -1338,11 +1340,9 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
       uint32_t npay = 0, v1 = 0;
       if (pr_r[u] >= 0 && pr_r[u] < p && k < D) {
         const int i = pr_i[u];
-        I->h_par[i] = nh_p[u];
-        I->h_perp[i] = nh_q[u];
+        I->h[i] = make_double2(nh_p[u], nh_q[u]);
         if (mode == kFieldCarry) {
-          I->hd_par[i] = nd_p[u];
-          I->hd_perp[i] = nd_q[u];
+          I->hd[i] = make_double2(nd_p[u], nd_q[u]);
         } else if (mode == kFieldDirty) {
           I->dirty[i] = 1;
         }
@@ -1438,10 +1438,8 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
   const double* __restrict__ Brp = I->rBr;
   const double* __restrict__ hkp = I->hk;
   int8_t* __restrict__ sp = I->s;
-  double* __restrict__ hpp = I->h_par;
-  double* __restrict__ hqp = I->h_perp;
-  double* __restrict__ hdp = I->hd_par;
-  double* __restrict__ hdq = I->hd_perp;
+  double2* __restrict__ hp2 = I->h;
+  double2* __restrict__ hd2 = I->hd;
   double* __restrict__ keyp = I->key;
   uint8_t* __restrict__ dirtyp = I->dirty;
   const int32_t mode = I->field_mode;
@@ -1579,18 +1577,18 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
       if (i >= 0) {
         const double da = two * (pre ? pf_a[h & 1] : Ap[sl]);
         const double db = two * (pre ? pf_b[h & 1] : Brp[sl]);
-        const double hp = hpp[i] + da;
-        const double hq = hqp[i] + db;
+        const double2 hi = hp2[i];
+        const double hp = hi.x + da;
+        const double hq = hi.y + db;
         if (mode == kFieldCarry) {
-          hdp[i] = hdp[i] + da;
-          hdq[i] = hdq[i] + db;
+          const double2 di = hd2[i];
+          hd2[i] = make_double2(di.x + da, di.y + db);
         } else if (mode == kFieldDirty) {
           dirtyp[i] = 1;
         }
         const int si = sp[i];
         const double kk = switching_key(si, hp, hq, hkp[i], pb, pc, ep, eq);
-        hpp[i] = hp;
-        hqp[i] = hq;
+        hp2[i] = make_double2(hp, hq);
         keyp[i] = kk;
         const int e = (int)(i >> l1s);
         if (atomicExch(&L.l1flag[e], 1) == 0) L.l1list[atomicAdd(&sh.n1, 1)] = e;

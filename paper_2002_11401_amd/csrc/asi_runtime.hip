@@ -415,10 +415,8 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   I.s = ds;
   I.field_mode = p->field_mode;
   I.dirty = dalloc<uint8_t>(s, n);
-  I.hd_par = dalloc<double>(s, n);
-  I.hd_perp = dalloc<double>(s, n);
-  I.h_par = dalloc<double>(s, n);
-  I.h_perp = dalloc<double>(s, n);
+  I.hd = dalloc<double2>(s, n);
+  I.h = dalloc<double2>(s, n);
   I.key = dalloc<double>(s, n);
   I.t1key = dalloc<double>(s, nsl);
   I.t1idx = dalloc<uint32_t>(s, nsl);
@@ -449,15 +447,12 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   s->nblocks = (n + kFieldBlock - 1) / kFieldBlock;
   s->blk_inst = dalloc<int32_t>(s, s->nblocks);
   s->blk_row0 = dalloc<int32_t>(s, s->nblocks);
-  if (!I.dirty || !I.hd_par || !I.hd_perp || !I.h_par || !I.h_perp || !I.key || !I.t1key || !I.t1idx ||
+  if (!I.dirty || !I.hd || !I.h || !I.key || !I.t1key || !I.t1idx ||
       !I.log_t || !I.log_j || !s->dI || !s->dR || !s->blk_inst || !s->blk_row0)
     return fail(ASI_ENOMEM, "device allocation failed (state)");
-  HIPCHK(hipMemsetAsync(I.h_par, 0, 8 * n, s->stream), s);
-  HIPCHK(hipMemsetAsync(I.h_perp, 0, 8 * n, s->stream), s);
-  HIPCHK(hipMemsetAsync(I.hd_par, 0, 8 * n, s->stream), s);
-  HIPCHK(hipMemsetAsync(I.hd_perp, 0, 8 * n, s->stream), s);
+  HIPCHK(hipMemsetAsync(I.h, 0, 16 * n, s->stream), s);
+  HIPCHK(hipMemsetAsync(I.hd, 0, 16 * n, s->stream), s);
   HIPCHK(hipMemsetAsync(I.dirty, 1, n, s->stream), s);
-  HIPCHK(hipMemsetAsync(I.h_perp, 0, 8 * n, s->stream), s);
   std::vector<int32_t> bi(s->nblocks, 0), br(s->nblocks);
   for (int64_t b = 0; b < s->nblocks; ++b) br[b] = (int32_t)(b * kFieldBlock);
   HIPCHK(hipMemcpyAsync(s->blk_inst, bi.data(), 4 * s->nblocks, hipMemcpyHostToDevice, s->stream),
@@ -626,8 +621,7 @@ asi_status asi_tune(asi_handle h, int64_t sample_steps, asi_tuning* out) {
     void* snap;
   };
   std::vector<Arr> arrs = {{I.s, (size_t)n, nullptr},          {I.dirty, (size_t)n, nullptr},
-                           {I.hd_par, 8 * (size_t)n, nullptr},  {I.hd_perp, 8 * (size_t)n, nullptr},
-                           {I.h_par, 8 * (size_t)n, nullptr},   {I.h_perp, 8 * (size_t)n, nullptr},
+                           {I.hd, 16 * (size_t)n, nullptr},     {I.h, 16 * (size_t)n, nullptr},
                            {I.key, 8 * (size_t)n, nullptr},     {I.ver, 4 * (size_t)n, nullptr},
                            {I.t1key, 8 * (size_t)nsl, nullptr}, {I.t1idx, 4 * (size_t)nsl, nullptr},
                            {I.step_flips + t0, 4 * (size_t)(t1 - t0), nullptr}};
@@ -767,12 +761,17 @@ asi_status asi_get_state(asi_handle h, int8_t* spins, double* h_par, double* h_p
   asi_status st = check_handle(h);
   if (st != ASI_OK) return st;
   if (spins) HIPCHK(hipMemcpyAsync(spins, h->hI.s, h->n, hipMemcpyDeviceToHost, h->stream), h);
-  if (h_par)
-    HIPCHK(hipMemcpyAsync(h_par, h->hI.h_par, 8 * h->n, hipMemcpyDeviceToHost, h->stream), h);
-  if (h_perp)
-    HIPCHK(hipMemcpyAsync(h_perp, h->hI.h_perp, 8 * h->n, hipMemcpyDeviceToHost, h->stream), h);
+  std::vector<double2> f;
+  if (h_par || h_perp) {
+    f.resize(h->n);
+    HIPCHK(hipMemcpyAsync(f.data(), h->hI.h, 16 * h->n, hipMemcpyDeviceToHost, h->stream), h);
+  }
   st = sync_and_check(h);
   if (st != ASI_OK) return st;
+  for (int64_t i = 0; i < (int64_t)f.size(); ++i) {
+    if (h_par) h_par[i] = f[i].x;
+    if (h_perp) h_perp[i] = f[i].y;
+  }
   if (step_out) *step_out = h->cur_step;
   return ASI_OK;
 }
