@@ -1060,19 +1060,27 @@ __device__ __forceinline__ void refill_select(const InstDev* I, const SpecLds& S
   __syncthreads();
 }
 
-// Window entries better than cold_max (all of them when the pool is empty).
-__device__ __forceinline__ int count_safe(const SpecLds& S, const SpecShared& sh) {
+
+// Window entries better than cold_max (all of them when the pool is
+// empty), counted by one wavefront (every lane gets the count): the safe
+// entries are a prefix of the window, so 64 segment ends locate the
+// boundary's segment, and one lane per entry of that segment finds it.
+__device__ __forceinline__ int count_safe_wave(const SpecLds& S, const SpecShared& sh) {
+  const int lane = threadIdx.x & 63;
   const int nx = sh.nx;
-  if (sh.ncold == 0) return nx;
+  if (sh.ncold == 0 || nx == 0) return nx;
   const double* k = win_k(S, sh.xb);
   const uint32_t* p = win_p(S, sh.xb);
   const uint32_t* v = win_v(S, sh.xb);
-  int lo = 0, hi = nx;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (better_e(k[mid], p[mid], v[mid], sh.cmk, sh.cmp, sh.cmv)) lo = mid + 1; else hi = mid;
-  }
-  return lo;
+  const double cmk = sh.cmk;
+  const uint32_t cmp = sh.cmp, cmv = sh.cmv;
+  const int step = (nx + 63) >> 6;
+  const int e = (lane + 1) * step - 1;
+  const bool ok = e < nx && better_e(k[e], p[e], v[e], cmk, cmp, cmv);
+  const int c = __popcll(__ballot(ok));
+  const int e2 = c * step + lane;
+  const bool ok2 = lane < step && e2 < nx && better_e(k[e2], p[e2], v[e2], cmk, cmp, cmv);
+  return c * step + __popcll(__ballot(ok2));
 }
 
 __device__ inline uint32_t hash_slot(uint32_t i) { return (i * 2654435761u) >> (32 - 12); }
@@ -1119,9 +1127,12 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
       status = 2;
       break;
     }
-    if (tid == 0) {
-      sh.safe = count_safe(S, sh);
-      sh.pause = (flips > flips0 && past(deadline)) ? 1 : 0;
+    if (tid < 64) {
+      const int sf = count_safe_wave(S, sh);
+      if (tid == 0) {
+        sh.safe = sf;
+        sh.pause = (flips > flips0 && past(deadline)) ? 1 : 0;
+      }
     }
     __syncthreads();
     const int pause = sh.pause;
@@ -1131,7 +1142,10 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
         refill_select(I, S, sh);
       else
         refill(I, S, sh);
-      if (tid == 0) sh.safe = count_safe(S, sh);
+      if (tid < 64) {
+        const int sf = count_safe_wave(S, sh);
+        if (tid == 0) sh.safe = sf;
+      }
       __syncthreads();
       if (sh.safe == 0) break;  // the pool held stale entries only
     }
