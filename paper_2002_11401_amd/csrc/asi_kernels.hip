@@ -1683,15 +1683,30 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
       double bk = 0.0;
       uint32_t bp = 0;
       // the lane's segment in groups of 8, each group's loads issued together
+      // (whole groups inside the arrays: four 16-byte key loads and one
+      // 8-byte spin load, the group starting on a 64-byte boundary)
       for (int m0 = 0; m0 < seg; m0 += 8) {
         double kk[8];
         int ss[8];
+        if (seg >= 8 && r0 + m0 + 8 <= n) {
+          const double2* k2 = reinterpret_cast<const double2*>(keyp + r0 + m0);
+          const uint64_t s8 = *reinterpret_cast<const uint64_t*>(sp + r0 + m0);
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-          const int64_t ii = r0 + m0 + m;
-          const bool ok = m0 + m < seg && ii < n;
-          kk[m] = ok ? keyp[ii] : 0.0;
-          ss[m] = ok ? sp[ii] : 0;
+          for (int m = 0; m < 4; ++m) {
+            const double2 v = k2[m];
+            kk[2 * m] = v.x;
+            kk[2 * m + 1] = v.y;
+          }
+#pragma unroll
+          for (int m = 0; m < 8; ++m) ss[m] = (int)(int8_t)(uint8_t)(s8 >> (8 * m));
+        } else {
+#pragma unroll
+          for (int m = 0; m < 8; ++m) {
+            const int64_t ii = r0 + m0 + m;
+            const bool ok = m0 + m < seg && ii < n;
+            kk[m] = ok ? keyp[ii] : 0.0;
+            ss[m] = ok ? sp[ii] : 0;
+          }
         }
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
