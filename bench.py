@@ -320,9 +320,9 @@ def main():
     ap.add_argument("--burst-ms", type=float, default=20.0, help="served: device time per step")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); independent instances "
-              "would shard across GPUs with no communication, which this build does not run.",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library drives one "
+              "device per process; independent instances would shard across GPUs with no "
+              "communication, but no multi-GPU path is implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
