@@ -944,8 +944,8 @@ __device__ __forceinline__ void refill(const InstDev* I, const SpecLds& S, SpecS
 // order) as the cold bound; staging is sorted and merged into the window,
 // whose overflow joins the pool and the bound, which stays exact.  Only
 // about kWin entries are sorted instead of the whole pool.  If more current
-// entries than staging holds lie above tau, the pass is discarded and the
-// full refill runs instead.
+// entries than staging holds lie above tau, or none does, the pass is
+// discarded and the full refill runs instead.
 __device__ __forceinline__ void refill_select(const InstDev* I, const SpecLds& S, SpecShared& sh) {
   const int tid = threadIdx.x, NT = blockDim.x, lane = tid & 63, wave = tid >> 6;
   const int cb = sh.cb;
@@ -1032,7 +1032,9 @@ __device__ __forceinline__ void refill_select(const InstDev* I, const SpecLds& S
     sh.wv[wave] = bv;
   }
   __syncthreads();
-  if (sh.over) {  // too many above tau: the full refill, from the same pool
+  // Too many current entries above tau, or none (ties at the top of the
+  // sample can put tau on the best key): the full refill, from the same pool.
+  if (sh.over || sh.ns == 0) {
     refill(I, S, sh);
     return;
   }
