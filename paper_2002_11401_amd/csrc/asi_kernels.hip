@@ -630,7 +630,7 @@ struct RelaxShared {
 
 // True once the deadline (device constant-rate clock; 0: none) has passed.
 __device__ inline bool past(uint64_t deadline) {
-  return deadline != 0 && wall_clock64() > deadline;
+  return deadline != 0 && (uint64_t)wall_clock64() > deadline;
 }
 
 // ------------------------------------------------------------ speculative relax
