@@ -69,7 +69,8 @@ typedef struct {
   const double* xy;          /* [2n] positions (x0, y0, x1, y1, ...), distinct  */
   const double* theta;       /* [n] island rotation: mhat = (cos, sin)(theta)   */
   const int8_t* spin0;       /* [n] start spins +-1, or NULL => all +1          */
-  const double* hk;          /* [n] coercive field h_k^(i) > 0 (Sec. II.G)      */
+  const double* hk;          /* [n] coercive field h_k^(i) > 0 (Sec. II.G), or
+                                NULL => drawn from hk_mean, k_disorder below  */
   double alpha;              /* dipolar coupling strength of Eq. 3, finite      */
   double neighbor_distance;  /* d >= 0: j is a neighbour of i iff
                                 (x_i-x_j)^2 + (y_i-y_j)^2 <= (d + 1e-9)^2      */
@@ -89,6 +90,14 @@ typedef struct {
                                 1 and 2 give bitwise identical results and
                                 fields that are a function of the spins only;
                                 0 differs from them by rounding.               */
+  /* Disorder of Sec. II.G, used when hk == NULL: h_k^(i) = hk_mean +
+     (k_disorder * hk_mean) * z_i, z_i the first Box-Muller normal of
+     Philox4x32-10 keyed (disorder_seed lo, hi) at counter (i, 0, 1, 0)
+     (u1, u2 formed as for the thermal field); draws below 1e-12 * hk_mean
+     are raised to it.  hk_mean > 0, k_disorder >= 0, both finite. */
+  double hk_mean;
+  double k_disorder;
+  uint64_t disorder_seed;
 } asi_params;
 
 /* Build an instance: copies the inputs, builds the neighbour lists and the

@@ -51,6 +51,7 @@ def lib():
         L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_normal_pair.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                       C.c_void_p]
+        L.orc_disorder_hk.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_uint64, C.c_void_p]
         _lib = L
     return _lib
 
@@ -75,6 +76,15 @@ def normal_pair(seed, c0, c1, tag=0):
     z = np.zeros(2)
     lib().orc_normal_pair(int(seed), int(c0), int(c1), int(tag), _vp(z))
     return z
+
+
+def disorder_hk(n, mean, k, seed):
+    """Coercive fields drawn from the disorder distribution (Sec. II.G):
+    mean + (k * mean) * z_i, z_i the first normal of counter (i, 0, 1, 0),
+    raised to 1e-12 * mean where below."""
+    out = np.zeros(int(n))
+    lib().orc_disorder_hk(int(n), float(mean), float(k), int(seed), _vp(out))
+    return out
 
 
 class Oracle:

@@ -255,6 +255,19 @@ void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) 
   for (int k = 0; k < 4; ++k) out[k] = o.v[k];
 }
 
+// Sec. II.G disorder: h_k^(i) = mean + (k * mean) * z_i with z_i the first
+// normal of counter (i, 0, 1, 0); draws below 1e-12 * mean are raised to it.
+void orc_disorder_hk(int64_t n, double mean, double k, uint64_t seed, double* out) {
+  const double sd = k * mean;
+  const double lo = 1e-12 * mean;
+  for (int64_t i = 0; i < n; ++i) {
+    double z0, z1;
+    normal_pair(seed, (uint32_t)i, 0u, 1u, &z0, &z1);
+    const double h = mean + sd * z0;
+    out[i] = h < lo ? lo : h;
+  }
+}
+
 void orc_normal_pair(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t tag, double* z) {
   normal_pair(seed, c0, c1, tag, &z[0], &z[1]);
 }

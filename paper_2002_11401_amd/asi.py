@@ -53,7 +53,9 @@ class AsiParams(C.Structure):
                 ("b", C.c_double), ("c", C.c_double), ("beta", C.c_double),
                 ("gamma", C.c_double), ("thermal_std", C.c_double),
                 ("thermal_seed", C.c_uint64), ("max_flips_per_step", C.c_int64),
-                ("flip_log_capacity", C.c_int64), ("field_mode", C.c_int32)]
+                ("flip_log_capacity", C.c_int64), ("field_mode", C.c_int32),
+                ("hk_mean", C.c_double), ("k_disorder", C.c_double),
+                ("disorder_seed", C.c_uint64)]
 
 
 class AsiInfo(C.Structure):
@@ -203,19 +205,23 @@ def _close_all():
 
 def _params(xy, theta, hk, spin0, alpha, neighbor_distance, b, c, beta, gamma,
             thermal_std=0.0, thermal_seed=0, max_flips_per_step=0, flip_log_capacity=0,
-            field_mode="carry"):
+            field_mode="carry", hk_mean=0.0, k_disorder=0.0, disorder_seed=0):
+    """hk None: the library draws the coercive fields from hk_mean,
+    k_disorder and disorder_seed (see asi_params in include/asi.h)."""
     keep = [np.ascontiguousarray(xy, dtype=np.float64).reshape(-1),
             np.ascontiguousarray(theta, dtype=np.float64),
-            np.ascontiguousarray(hk, dtype=np.float64),
+            None if hk is None else np.ascontiguousarray(hk, dtype=np.float64),
             None if spin0 is None else np.ascontiguousarray(spin0, dtype=np.int8)]
     n = len(keep[1])
-    if len(keep[0]) != 2 * n or len(keep[2]) != n or (keep[3] is not None and len(keep[3]) != n):
+    if (len(keep[0]) != 2 * n or (keep[2] is not None and len(keep[2]) != n) or
+            (keep[3] is not None and len(keep[3]) != n)):
         raise ValueError("xy must be [n,2]; theta, hk, spin0 must be [n]")
     p = AsiParams(C.sizeof(AsiParams), n, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[3]),
                   _ptr(keep[2]), float(alpha), float(neighbor_distance), float(b), float(c),
                   float(beta), float(gamma), float(thermal_std), int(thermal_seed),
                   int(max_flips_per_step), int(flip_log_capacity),
-                  FIELD_MODES[field_mode] if isinstance(field_mode, str) else int(field_mode))
+                  FIELD_MODES[field_mode] if isinstance(field_mode, str) else int(field_mode),
+                  float(hk_mean), float(k_disorder), int(disorder_seed))
     return p, keep
 
 
@@ -224,12 +230,13 @@ class Sim:
 
     def __init__(self, xy, theta, hk, spin0=None, *, alpha, neighbor_distance, b, c, beta,
                  gamma, thermal_std=0.0, thermal_seed=0, H=None, max_flips_per_step=0,
-                 flip_log_capacity=0, field_mode="carry", device="torch"):
+                 flip_log_capacity=0, field_mode="carry", device="torch", hk_mean=0.0,
+                 k_disorder=0.0, disorder_seed=0):
         L = library()
         self._dev = device if not isinstance(device, str) else make_device(device)
         p, keep = _params(xy, theta, hk, spin0, alpha, neighbor_distance, b, c, beta, gamma,
                           thermal_std, thermal_seed, max_flips_per_step, flip_log_capacity,
-                          field_mode)
+                          field_mode, hk_mean, k_disorder, disorder_seed)
         h = C.c_void_p()
         _check(L.asi_create(C.byref(p), C.byref(self._dev.struct), C.byref(h)))
         self._h = h

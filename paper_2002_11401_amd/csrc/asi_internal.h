@@ -105,6 +105,8 @@ struct RunDev {
   int64_t step_acc;
 };
 
+// Coercive fields drawn from the disorder distribution (asi_params.hk == NULL).
+void launch_draw_hk(double* hk, int64_t n, double mean, double k, uint64_t seed, hipStream_t st);
 void launch_neighbour_count(const double* x, const double* y, const int32_t* cellx,
                             const int32_t* celly, const int32_t* cell_start,
                             const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,

@@ -170,6 +170,25 @@ __device__ inline int64_t slot_of(int64_t i, int32_t D, int32_t k) {
 }
 
 // ------------------------------------------------------------ neighbours
+// Coercive fields of Sec. II.G drawn on the device (hk == NULL): the first
+// Box-Muller normal of Philox4x32-10 at counter (i, 0, 1, 0), uniforms
+// formed as for the thermal field.
+__global__ void k_draw_hk(double* __restrict__ hk, int64_t n, double mean, double k,
+                          uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const U4 o = philox4x32_10(U4{(uint32_t)i, 0u, 1u, 0u}, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t a = ((((uint64_t)o.x) << 32) | o.y) >> 11;
+  const uint64_t b = ((((uint64_t)o.z) << 32) | o.w) >> 11;
+  const double u1 = (double)(a + 1) * 0x1p-53;
+  const double u2 = (double)b * 0x1p-53;
+  const double z0 = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  const double sd = k * mean;
+  const double h = mean + sd * z0;
+  const double lo = 1e-12 * mean;
+  hk[i] = h < lo ? lo : h;
+}
+
 // Cells of side >= the cutoff, magnets sorted by cell (ascending index
 // within a cell); a magnet's neighbours lie in its 3 x 3 cell block.
 __global__ void k_nb_count(const double* __restrict__ x, const double* __restrict__ y,
@@ -1910,6 +1929,12 @@ __global__ void k_set_run(RunDev* R, int64_t t, int64_t t_end, int32_t active,
 }  // namespace
 
 // ------------------------------------------------------------ launchers
+void launch_draw_hk(double* hk, int64_t n, double mean, double k, uint64_t seed, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_draw_hk, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, hk, n, mean, k,
+                     seed);
+}
+
 void launch_neighbour_count(const double* x, const double* y, const int32_t* cellx,
                             const int32_t* celly, const int32_t* cell_start,
                             const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,

@@ -209,7 +209,10 @@ asi_status validate(const asi_params* p) {
   if (p->struct_size != sizeof(asi_params))
     return fail(ASI_EINVAL, "asi_params.struct_size mismatch");
   if (p->n < 1 || p->n >= (int64_t)0x7fffffff) return fail(ASI_EINVAL, "n out of range");
-  if (!p->xy || !p->theta || !p->hk) return fail(ASI_EINVAL, "xy, theta and hk are required");
+  if (!p->xy || !p->theta) return fail(ASI_EINVAL, "xy and theta are required");
+  if (!p->hk && (!(p->hk_mean > 0.0) || !std::isfinite(p->hk_mean) || !(p->k_disorder >= 0.0) ||
+                 !std::isfinite(p->k_disorder)))
+    return fail(ASI_EINVAL, "hk is NULL: hk_mean must be finite and > 0, k_disorder finite and >= 0");
   if (!(std::isfinite(p->alpha))) return fail(ASI_EINVAL, "alpha must be finite");
   if (!(p->neighbor_distance >= 0.0) || !std::isfinite(p->neighbor_distance))
     return fail(ASI_EINVAL, "neighbor_distance must be finite and >= 0");
@@ -226,7 +229,7 @@ asi_status validate(const asi_params* p) {
     if (!std::isfinite(p->xy[2 * i]) || !std::isfinite(p->xy[2 * i + 1]) ||
         !std::isfinite(p->theta[i]))
       return fail(ASI_EINVAL, "non-finite position or angle at magnet " + std::to_string(i));
-    if (!(p->hk[i] > 0.0) || !std::isfinite(p->hk[i]))
+    if (p->hk && (!(p->hk[i] > 0.0) || !std::isfinite(p->hk[i])))
       return fail(ASI_EINVAL, "hk must be finite and > 0 (magnet " + std::to_string(i) + ")");
     if (p->spin0 && p->spin0[i] != 1 && p->spin0[i] != -1)
       return fail(ASI_EINVAL, "spin0 values must be +1 or -1");
@@ -325,7 +328,12 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   HIPCHK(hipMemcpyAsync(dy, y.data(), 8 * n, hipMemcpyHostToDevice, s->stream), s);
   HIPCHK(hipMemcpyAsync(dmx, mx.data(), 8 * n, hipMemcpyHostToDevice, s->stream), s);
   HIPCHK(hipMemcpyAsync(dmy, my.data(), 8 * n, hipMemcpyHostToDevice, s->stream), s);
-  HIPCHK(hipMemcpyAsync(dhk, p->hk, 8 * n, hipMemcpyHostToDevice, s->stream), s);
+  if (p->hk) {
+    HIPCHK(hipMemcpyAsync(dhk, p->hk, 8 * n, hipMemcpyHostToDevice, s->stream), s);
+  } else {
+    launch_draw_hk(dhk, n, p->hk_mean, p->k_disorder, p->disorder_seed, s->stream);
+    HIPCHK(hipGetLastError(), s);
+  }
   HIPCHK(hipMemcpyAsync(ds, s0.data(), n, hipMemcpyHostToDevice, s->stream), s);
   HIPCHK(hipMemcpyAsync(dcx, cx.data(), 4 * n, hipMemcpyHostToDevice, s->stream), s);
   HIPCHK(hipMemcpyAsync(dcy, cy.data(), 4 * n, hipMemcpyHostToDevice, s->stream), s);
@@ -1198,7 +1206,7 @@ asi_status server_admit(asi_server* S) {
     asi_params p = J.p;
     p.xy = J.xy.data();
     p.theta = J.theta.data();
-    p.hk = J.hk.data();
+    p.hk = J.hk.empty() ? nullptr : J.hk.data();
     p.spin0 = J.spin0.empty() ? nullptr : J.spin0.data();
     asi_handle h = nullptr;
     asi_status st = asi_create(&p, &S->cdev, &h);
@@ -1296,7 +1304,7 @@ asi_status asi_server_submit(asi_server_t S, const asi_params* p, int64_t n_step
   J->p = *p;
   J->xy.assign(p->xy, p->xy + 2 * p->n);
   J->theta.assign(p->theta, p->theta + p->n);
-  J->hk.assign(p->hk, p->hk + p->n);
+  if (p->hk) J->hk.assign(p->hk, p->hk + p->n);
   if (p->spin0) J->spin0.assign(p->spin0, p->spin0 + p->n);
   J->H.assign(h_xy, h_xy + 2 * n_steps);
   J->K = n_steps;

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     # asi_params: u32 + pad, i64, 4 pointers, 8 doubles, u64, 2 x i64
-    assert C.sizeof(asi.AsiParams) == 8 + 8 + 4 * 8 + 7 * 8 + 8 + 8 + 8 + 8
+    assert C.sizeof(asi.AsiParams) == 8 + 8 + 4 * 8 + 7 * 8 + 8 + 8 + 8 + 8 + 3 * 8
     assert C.sizeof(asi.AsiDevice) == 4 * 8
     assert C.sizeof(asi.AsiInfo) == 8 + 8 + 4 + 4 + 8 + 8 + 8
     assert C.sizeof(asi.AsiServerStats) == 4 * 8 + 4 * 8

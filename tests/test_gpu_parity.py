@@ -282,6 +282,24 @@ def test_large_pool_with_tied_keys():
     assert_same_flips(sim.flip_log(), r, sim.state()[0], o.spins())
 
 
+def test_library_draws_the_disorder():
+    """h_k not given: the library draws it (Sec. II.G) with the generator the
+    oracle implements independently; flips match the oracle bit for bit."""
+    import dataclasses
+    w = W.square_10x10_triangle()
+    hk = N.disorder_hk(w.n, 0.2, 0.05, 21)
+    assert not np.array_equal(hk, w.hk)
+    say("library-drawn disorder", w.n)
+    sim = asi.Sim(w.xy, w.theta, None, w.spin0, H=w.H, hk_mean=0.2, k_disorder=0.05,
+                  disorder_seed=21, **w.params())
+    sim.run()
+    o, r = oracle_run(dataclasses.replace(w, hk=hk))
+    assert_same_flips(sim.flip_log(), r, sim.state()[0], o.spins())
+    assert_fields_close(o, sim, w.H[-1], w.n_steps - 1)
+    with pytest.raises(asi.AsiError):
+        asi.Sim(w.xy, w.theta, None, w.spin0, H=w.H, hk_mean=0.0, **w.params())
+
+
 # ------------------------------------------------------------------ autotuner
 @pytest.mark.parametrize("family,d,thermal", [("kagome", 3, 0.005), ("pinwheel", 8, 0.0),
                                               ("square", 4, 0.003)])

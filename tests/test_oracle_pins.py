@@ -318,6 +318,24 @@ def test_p8_philox_known_answers():
         assert got[0].tolist() == out
 
 
+def test_p8_disorder_draw_follows_its_generator_and_moments():
+    """Sec. II.G disorder drawn inside the library when h_k is not given:
+    mean + (k * mean) * z_i with z_i the first normal of counter
+    (i, 0, 1, 0); pinned to the tier-0 generator, to the stated moments and
+    to the clip at 1e-12 * mean."""
+    n = 200000
+    h = N.disorder_hk(n, 0.2, 0.05, 9)
+    z0, _ = D.normal_pairs(9, np.arange(64), np.zeros(64, dtype=np.int64), tag=1)
+    expect = 0.2 + (0.05 * 0.2) * z0
+    assert np.all(np.abs(h[:64] - expect) <= 8 * np.spacing(expect))
+    assert abs(h.mean() - 0.2) < 1e-4 and abs(h.std() - 0.01) < 1e-4
+    assert stats.kstest((h - 0.2) / 0.01, "norm").pvalue > 1e-3
+    wide = N.disorder_hk(4000, 0.2, 5.0, 3)
+    lo = 1e-12 * 0.2
+    assert wide.min() == lo and np.mean(wide == lo) > 0.4   # about half clipped
+    assert not np.array_equal(h[:100], N.disorder_hk(100, 0.2, 0.05, 10))
+
+
 def test_p8_two_oracle_tiers_agree_bitwise_and_normals_are_normal():
     """Raw Philox words agree bit for bit between the tiers; the Box-Muller
     normals agree to a few ULP (numpy's and glibc's log/cos/sin may differ in
