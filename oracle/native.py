@@ -43,6 +43,7 @@ def lib():
         L.orc_neighbours.argtypes = [P, C.c_void_p, C.c_void_p]
         L.orc_set_spins.argtypes = [P, C.c_void_p]
         L.orc_get_spins.argtypes = [P, C.c_void_p]
+        L.orc_set_local_field.argtypes = [P, C.c_int64, C.c_void_p]
         L.orc_fields.argtypes = [P, dp, C.c_int64] + [C.c_void_p] * 5
         L.orc_run.restype = C.c_int
         L.orc_run.argtypes = [P, C.c_int64, dp, C.c_int64, C.c_int64, C.c_void_p,
@@ -104,7 +105,10 @@ class Oracle:
 
     @classmethod
     def from_workload(cls, w):
-        return cls(w.xy, w.theta, w.hk, **w.params())
+        o = cls(w.xy, w.theta, w.hk, **w.params())
+        if getattr(w, "h_loc", None) is not None:
+            o.set_local_field(w.h_loc)
+        return o
 
     def close(self):
         if self._h:
@@ -136,8 +140,25 @@ class Oracle:
         lib().orc_get_spins(self._h, _vp(s))
         return s
 
+    def set_local_field(self, h_loc):
+        """Local external field (Sec. II.D): (n, 2) for every step, (K, n, 2)
+        one slab per step, None for none."""
+        if h_loc is None:
+            self._loc = None
+            self._loc_k = 0
+            lib().orc_set_local_field(self._h, 0, None)
+            return
+        a = np.ascontiguousarray(h_loc, dtype=np.float64)
+        if a.ndim == 2:
+            a = a[None]
+        assert a.ndim == 3 and a.shape[1:] == (self.n, 2), a.shape
+        self._loc = a
+        self._loc_k = a.shape[0]
+        lib().orc_set_local_field(self._h, a.shape[0], _vp(a))
+
     def fields(self, H, t):
         """(h_par, h_perp, scale) for the current spins at step t."""
+        assert getattr(self, "_loc_k", 0) <= 1 or t < self._loc_k
         H = np.ascontiguousarray(H, dtype=np.float64)
         hp, hq, sc = (np.zeros(self.n) for _ in range(3))
         lib().orc_fields(self._h, _dp(H), int(t), _vp(hp), _vp(hq), None, None, _vp(sc))

@@ -16,7 +16,9 @@
 //           r = r_i - r_j, N(i) = { j != i : |r_i - r_j| <= d } (Sec. II.C:
 //           neighbourhood in lattice units; inclusive, tested as
 //           dx^2 + dy^2 <= (d + 1e-9)^2), summed in ascending j.
-//   Eq. 2   h_i = h_dip_i + h_ext + h_th_i           (xy frame)
+//   Eq. 2   h_i = h_dip_i + h_ext_i + h_th_i         (xy frame)
+//           h_ext_i = H[t] + hloc_i(t): the global field of step t plus the
+//           magnet's own local field (Sec. II.D), static or one per step
 //           h_par = h_i . mhat_i, h_perp = h_i . mhat_perp_i,
 //           mhat_perp_i = (-sin th_i, cos th_i)       (Sec. II.F, Fig. 2)
 //   Eq. 5   L_i = (|h_par|/(b hk_i))^(2/gamma) + (|h_perp|/(c hk_i))^(2/beta)
@@ -103,6 +105,8 @@ struct Model {
   std::vector<double> gabs;         // alpha * sum_j |g_ij| per row (scale)
   std::vector<int8_t> s;
   std::vector<double> hdx, hdy;     // alpha * sum_j s_j g_ij
+  std::vector<double> loc;          // [loc_k][n][2] local external field
+  int64_t loc_k = 0;                // 0 none, 1 static, else one per step
 };
 
 void build_neighbours(Model& M) {
@@ -196,8 +200,16 @@ void dipolar_row(Model& M, int64_t i) {
 
 struct StepFields {
   double Hx = 0, Hy = 0;
+  const double* loc = nullptr;   // [n][2] local field of this step, or none
   std::vector<double> thx, thy;  // empty when sigma_th == 0
 };
+
+// Local external field of step t (none before the first step).
+const double* local_for_step(const Model& M, int64_t t) {
+  if (M.loc_k == 0 || t < 0) return nullptr;
+  const int64_t k = (M.loc_k == 1) ? 0 : t;
+  return &M.loc[(size_t)(2 * k * M.n)];
+}
 
 // Step t < 0 is the state before the first field step: no thermal draw.
 void thermal_for_step(const Model& M, int64_t t, StepFields& F) {
@@ -217,6 +229,7 @@ struct Eval { double hpar, hperp, L; bool flip; };
 Eval evaluate(const Model& M, const StepFields& F, int64_t i) {
   double hx = M.hdx[i] + F.Hx;
   double hy = M.hdy[i] + F.Hy;
+  if (F.loc) { hx = hx + F.loc[2 * i]; hy = hy + F.loc[2 * i + 1]; }
   if (!F.thx.empty()) { hx = hx + F.thx[i]; hy = hy + F.thy[i]; }
   Eval ev;
   ev.hpar = hx * M.mx[i] + hy * M.my[i];
@@ -240,6 +253,7 @@ struct Gaps {
 
 inline void note(Gaps& G, const Model& M, const StepFields& F, int64_t i, const Eval& ev) {
   double scale = M.gabs[i] + std::hypot(F.Hx, F.Hy);
+  if (F.loc) scale += std::hypot(F.loc[2 * i], F.loc[2 * i + 1]);
   if (!F.thx.empty()) scale += std::hypot(F.thx[i], F.thy[i]);
   if (scale > 0.0) G.min_par_rel = std::min(G.min_par_rel, std::fabs(ev.hpar) / scale);
   if ((double)M.s[i] * ev.hpar < 0.0) G.min_thresh_rel = std::min(G.min_thresh_rel, std::fabs(ev.L - 1.0));
@@ -311,19 +325,29 @@ void orc_set_spins(void* h, const int8_t* s) {
   for (int64_t i = 0; i < M.n; ++i) dipolar_row(M, i);
 }
 
+// Local external field (Sec. II.D): loc[k][n][2] for k < loc_k; loc_k = 1
+// applies slab 0 at every step, loc_k > 1 gives step t slab t; 0 removes it.
+void orc_set_local_field(void* h, int64_t loc_k, const double* loc) {
+  Model& M = *static_cast<Model*>(h);
+  M.loc_k = loc_k;
+  M.loc.assign(loc, loc + (size_t)(2 * loc_k * M.n));
+}
+
 void orc_get_spins(void* h, int8_t* s) {
   Model& M = *static_cast<Model*>(h);
   std::memcpy(s, M.s.data(), M.n);
 }
 
 // Total fields (h_par, h_perp) at step t under applied field H (2 doubles),
-// for the current spins; `scale` gets the summand scale
-// alpha*sum|g| + |H| + |h_th| per magnet.  Any output may be NULL.
+// for the current spins (plus the local field of step t, if set); `scale`
+// gets the summand scale alpha*sum|g| + |H| + |hloc| + |h_th| per magnet.
+// With a local series, t must be below its length.  Any output may be NULL.
 void orc_fields(void* h, const double* H, int64_t t, double* hpar, double* hperp,
                 double* hdx, double* hdy, double* scale) {
   Model& M = *static_cast<Model*>(h);
   StepFields F;
   F.Hx = H[0]; F.Hy = H[1];
+  F.loc = local_for_step(M, t);
   thermal_for_step(M, t, F);
   for (int64_t i = 0; i < M.n; ++i) {
     Eval ev = evaluate(M, F, i);
@@ -333,6 +357,7 @@ void orc_fields(void* h, const double* H, int64_t t, double* hpar, double* hperp
     if (hdy) hdy[i] = M.hdy[i];
     if (scale) {
       double sc = M.gabs[i] + std::hypot(F.Hx, F.Hy);
+      if (F.loc) sc += std::hypot(F.loc[2 * i], F.loc[2 * i + 1]);
       if (!F.thx.empty()) sc += std::hypot(F.thx[i], F.thy[i]);
       scale[i] = sc;
     }
@@ -354,8 +379,9 @@ int orc_run(void* h, int64_t K, const double* H, int64_t t_begin, int64_t t_end,
   std::vector<char> in_set(M.n, 0);
   StepFields F;
   for (int64_t t = t_begin; t < t_end && status == 0; ++t) {
-    if (t < 0 || t >= K) { status = -1; break; }
+    if (t < 0 || t >= K || (M.loc_k > 1 && t >= M.loc_k)) { status = -1; break; }
     F.Hx = H[2 * t]; F.Hy = H[2 * t + 1];
+    F.loc = local_for_step(M, t);
     thermal_for_step(M, t, F);
     std::set<std::pair<double, int32_t>> cand;   // (-L_i, i): begin() = max L, min i
     for (int64_t i = 0; i < M.n; ++i) {

@@ -120,6 +120,37 @@ def rotating(n_steps: int, amp: float, steps_per_rev: int, phase_deg: float = 0.
     return np.ascontiguousarray(np.stack([amp * np.cos(phi), amp * np.sin(phi)], axis=1))
 
 
+# per-magnet (local and spatial) fields, Sec. II.D: arrays h_loc[i] or
+# h_loc[t][i], added to the global H[t] by the model
+def spatial_gradient(xy: np.ndarray, grad: float, angle_deg: float, axis_deg: float = 0.0):
+    """Static spatial field h(r) = grad * (r . u) * e, sampled at the
+    positions: strength linear in the coordinate along u = (cos, sin)(axis)
+    (measured from the centre of the positions), direction e at angle_deg."""
+    u = np.array([math.cos(math.radians(axis_deg)), math.sin(math.radians(axis_deg))])
+    xy = np.asarray(xy, dtype=np.float64)
+    r = (xy - xy.mean(axis=0)) @ u
+    return _along(grad * r, angle_deg)
+
+
+def travelling_wave(xy: np.ndarray, n_steps: int, amp: float, wavelength: float,
+                    steps_per_period: int, angle_deg: float):
+    """Spatial field of every step, h(r, t) = amp * sin(2 pi (x / wavelength
+    - t / steps_per_period)) * e: a wave moving along x, direction e at
+    angle_deg.  Returns [n_steps, n, 2]."""
+    x = np.asarray(xy, dtype=np.float64)[:, 0]
+    t = np.arange(int(n_steps), dtype=np.float64)[:, None]
+    h = amp * np.sin(2.0 * np.pi * (x[None, :] / wavelength - t / float(steps_per_period)))
+    a = math.radians(angle_deg)
+    return np.ascontiguousarray(np.stack([h * math.cos(a), h * math.sin(a)], axis=2))
+
+
+def random_local(n: int, n_slabs: int, amp: float, seed: int):
+    """Independent N(0, amp^2) components per magnet (and per step when
+    n_slabs > 1), numpy PCG64 from `seed`: [n, 2] or [n_slabs, n, 2]."""
+    z = np.random.default_rng(int(seed)).standard_normal((int(n_slabs), int(n), 2)) * amp
+    return np.ascontiguousarray(z[0] if n_slabs == 1 else z)
+
+
 # --------------------------------------------------------------------------
 # random inputs
 # --------------------------------------------------------------------------
@@ -165,6 +196,9 @@ class Workload:
     thermal_std: float = 0.0
     thermal_seed: int = 0
     meta: Dict = dataclasses.field(default_factory=dict)
+    # per-magnet external field added to H (Sec. II.D): [n,2] static or
+    # [K,n,2] one slab per step; None for the global field alone
+    h_loc: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:

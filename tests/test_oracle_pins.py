@@ -392,3 +392,72 @@ def test_p9_tiers_agree_on_square10_triangle():
     assert list(zip(r["step"].tolist(), r["idx"].tolist())) == log0
     assert np.array_equal(s0, s1)
     assert len(log0) >= w.n   # a triangle sweep reverses the array and back
+
+
+# ---------------------------------------------------------------- P11: local fields
+@pytest.mark.parametrize("n_slabs", [1, 40])
+def test_p11_local_fields_on_independent_magnets(n_slabs):
+    """alpha = 0 with a per-magnet external field (Sec. II.D): every magnet
+    switches at the first step at which its own astroid condition holds
+    under H[t] + h_loc(i, t), and within a step in descending Eq. 5 LHS.  The
+    schedule follows from each magnet's own field alone, so a local field
+    that is dropped, read for the wrong magnet or step, or added with the
+    wrong sign moves it."""
+    n, K = 60, 40
+    xy, theta = W.random_cloud(n, 11, min_sep=0.4)
+    hk = W.disorder_hk(n, 0.2, 0.05, 11)
+    H = W.linear_ramp(K, 0.05, -0.05, 20.0)
+    loc = W.random_local(n, n_slabs, 0.12, 12)
+    b, c, beta, gamma = 0.38, 1.0, 1.5, 3.9
+    spins0 = np.random.default_rng(13).choice([-1, 1], n).astype(np.int8)
+    o = N.Oracle(**_model(xy, theta, hk, 0.0, 5.0, b, c, beta, gamma))
+    o.set_spins(spins0)
+    o.set_local_field(loc)
+    r = o.run(H)
+    mx, my = np.cos(theta), np.sin(theta)
+    s = spins0.astype(float).copy()
+    expect = []
+    for t in range(K):
+        h = H[t][None, :] + (loc if n_slabs == 1 else loc[t])
+        hp = h[:, 0] * mx + h[:, 1] * my
+        hq = h[:, 1] * mx - h[:, 0] * my
+        L = (np.abs(hp) / (b * hk)) ** (2 / gamma) + (np.abs(hq) / (c * hk)) ** (2 / beta)
+        ok = np.nonzero((s * hp < 0) & (L > 1))[0]
+        for i in sorted(ok, key=lambda i: (-L[i], i)):
+            expect.append((t, i))
+            s[i] = -s[i]
+    got = list(zip(r["step"].tolist(), r["idx"].tolist()))
+    assert got == expect
+    assert len(got) > (n // 3 if n_slabs == 1 else 2 * n)
+    # without the local field far fewer magnets switch under this weak ramp
+    o.set_spins(spins0)
+    o.set_local_field(None)
+    assert o.run(H)["n_flips"] < len(got) // 2
+
+
+@pytest.mark.parametrize("series", [False, True])
+def test_p11_uniform_local_field_equals_global_field(series):
+    """A local field that is the same vector c(t) on every magnet is a
+    global field: an interacting array under H[t] plus the local c(t)
+    switches exactly as under the global field H[t] + c(t) (static c, or one
+    per step, which also pins the slab a step reads)."""
+    w = W.square_10x10_triangle()
+    n, K = w.n, w.n_steps
+    cs = W.rotating(K, 0.03, 7) if series else np.tile([0.02, -0.035], (K, 1))
+    ref = N.Oracle.from_workload(w)
+    ref.set_spins(w.spin0)
+    r_glob = ref.run(w.H + cs)
+    o = N.Oracle.from_workload(w)
+    o.set_spins(w.spin0)
+    o.set_local_field(np.repeat(cs[:, None, :], n, axis=1) if series else np.tile(cs[0], (n, 1)))
+    r_loc = o.run(w.H)
+    assert r_loc["n_flips"] == r_glob["n_flips"] > w.n
+    assert np.array_equal(r_loc["step"], r_glob["step"])
+    assert np.array_equal(r_loc["idx"], r_glob["idx"])
+    assert np.array_equal(o.spins(), ref.spins())
+    # and the shifted field changes the run: the comparison is not vacuous
+    plain = N.Oracle.from_workload(w)
+    plain.set_spins(w.spin0)
+    r_plain = plain.run(w.H)
+    assert not (r_plain["n_flips"] == r_glob["n_flips"] and
+                np.array_equal(r_plain["idx"], r_glob["idx"]))
