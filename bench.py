@@ -92,6 +92,11 @@ def cpu_baseline(w, target_s: float = 15.0):
 
 def bench_plain(args, asi, workloads, torch):
     w = workloads.NAMED[args.workload]()
+    if args.local_field == "gradient":
+        # static spatial field on top of the global one (Sec. II.D): a
+        # gradient along x, 0.02 from the centre to the edge, at 200 deg
+        span = float(np.ptp(w.xy[:, 0])) / 2
+        w.h_loc = workloads.spatial_gradient(w.xy, 0.02 / span, 200.0, 0.0)
     K = w.n_steps if args.steps is None else min(args.steps, w.n_steps)
     # every step re-gathers every row: the measured full-field pass
     sim = asi.Sim.from_workload(w, field_mode="full")
@@ -127,7 +132,8 @@ def bench_plain(args, asi, workloads, torch):
         "config": {"workload": w.name, "magnets": N, "neighbour_pairs": E,
                    "max_degree": info["max_degree"], "neighbor_distance": w.neighbor_distance,
                    "thermal_std": w.thermal_std, "protocol_steps": w.n_steps,
-                   "field_pass": "full every step", "parallelism": "single instance, one GPU"},
+                   "field_pass": "full every step", "parallelism": "single instance, one GPU",
+                   "local_field": args.local_field},
         "flips_per_s": flips / dt,
         "flips": flips,
         "field_calcs_per_s": N * K / dt,
@@ -140,7 +146,8 @@ def bench_plain(args, asi, workloads, torch):
                   "flips_per_s_in_kernel": flips / max(1e-9, tm["relax_ms"] / 1e3)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": recorded_traffic() if w.name == "kagome577_rotating" else None,
+                     "traffic": (recorded_traffic() if w.name == "kagome577_rotating"
+                                 and args.local_field == "none" else None),
                      "kernel": ("k_field_hd (full-field pass, a workgroup per 64-row slice)"
                                 if info["max_degree"] >= HD_MIN_DEGREE
                                 else "k_field (full-field pass, a lane per row)")},
@@ -305,6 +312,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--mode", choices=["plain", "batched", "served"], default="plain")
     ap.add_argument("--workload", default="kagome577_rotating")
+    ap.add_argument("--local-field", default="none", choices=["none", "gradient"],
+                    help="plain: add a static per-magnet spatial field")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--count", type=int, default=256, help="batched: instances")

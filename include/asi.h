@@ -109,6 +109,17 @@ asi_status asi_create(const asi_params* params, const asi_device* dev, asi_handl
  * global field (x, y) of step k, 0 <= k < n_steps.  Copied. */
 asi_status asi_set_field_protocol(asi_handle h, int64_t n_steps, const double* h_xy);
 
+/* Per-magnet external field (Sec. II.D), added to the global H[t] of every
+ * step: the external field of magnet i at step t is H[t] + h_loc(i, t), with
+ * h_loc(i, t) = (h_loc[2*(k*n + i)], h_loc[2*(k*n + i) + 1]) and k = 0 when
+ * n_slabs == 1 (a static local or spatial field, e.g. a gradient sampled at
+ * the positions), k = t when n_slabs equals the protocol length (a local
+ * time series).  n_slabs == 0 removes it.  Copied to the device (16 * n *
+ * n_slabs bytes), host memory; ASI_EINVAL for any other n_slabs, a NULL
+ * h_loc with n_slabs > 0 or a non-finite value.  While a series (n_slabs >
+ * 1) is set, asi_set_field_protocol accepts only the same length. */
+asi_status asi_set_local_field(asi_handle h, int64_t n_slabs, const double* h_loc);
+
 /* Relax under the current step's fields (Sec. II.H) without advancing t.
  * flips_out (may be NULL) receives the number of flips of this call. */
 asi_status asi_relax(asi_handle h, int64_t* flips_out);
@@ -158,7 +169,8 @@ typedef struct {
   int32_t relax_waves;      /* wavefronts of the relax workgroup                 */
   int64_t device_bytes;     /* device memory held by the handle                  */
   double field_pass_bytes;  /* algorithmic bytes of one full-field pass:
-                               20 per neighbour pair + 53 per magnet            */
+                               20 per neighbour pair + 53 per magnet, + 16
+                               per magnet with a local field set              */
   int64_t flip_log_capacity;/* flip-log entries kept (asi_params)               */
 } asi_info;
 asi_status asi_get_info(asi_handle h, asi_info* out);

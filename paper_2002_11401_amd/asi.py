@@ -87,6 +87,7 @@ I64P = C.POINTER(C.c_int64)
 SIGNATURES = {
     "asi_create": [C.POINTER(AsiParams), C.POINTER(AsiDevice), C.POINTER(C.c_void_p)],
     "asi_set_field_protocol": [P, C.c_int64, P],
+    "asi_set_local_field": [P, C.c_int64, P],
     "asi_relax": [P, I64P],
     "asi_run": [P, C.c_int64, C.c_int64, I64P],
     "asi_get_state": [P, P, P, P, I64P],
@@ -248,7 +249,10 @@ class Sim:
 
     @classmethod
     def from_workload(cls, w, device="torch", **kw):
-        return cls(w.xy, w.theta, w.hk, w.spin0, H=w.H, device=device, **w.params(), **kw)
+        sim = cls(w.xy, w.theta, w.hk, w.spin0, H=w.H, device=device, **w.params(), **kw)
+        if getattr(w, "h_loc", None) is not None:
+            sim.set_local_field(w.h_loc)
+        return sim
 
     @property
     def handle(self):
@@ -271,6 +275,20 @@ class Sim:
         H = np.ascontiguousarray(H, dtype=np.float64).reshape(-1, 2)
         _check(library().asi_set_field_protocol(self.handle, len(H), _ptr(H)))
         self.K = len(H)
+
+    def set_local_field(self, h_loc):
+        """Per-magnet external field added to H[t] (Sec. II.D): an (n, 2)
+        array applies at every step, a (K, n, 2) array gives step t its own
+        slab; None removes it."""
+        if h_loc is None:
+            _check(library().asi_set_local_field(self.handle, 0, None))
+            return
+        a = np.ascontiguousarray(h_loc, dtype=np.float64)
+        if a.ndim == 2:
+            a = a[None]
+        if a.ndim != 3 or a.shape[1] != self.n or a.shape[2] != 2:
+            raise ValueError("h_loc must be (n, 2) or (K, n, 2)")
+        _check(library().asi_set_local_field(self.handle, a.shape[0], _ptr(a)))
 
     def run(self, t_begin=0, t_end=None) -> int:
         t_end = self.K if t_end is None else int(t_end)

@@ -56,6 +56,8 @@ struct InstDev {
   uint64_t seed;          // thermal Philox key
   const double* H;        // [K][2] applied field per step
   int64_t K;
+  const double2* hloc;    // [hloc_k][n] per-magnet external field (x, y), or null
+  int64_t hloc_k;         // 1: the same field at every step; else one per step (== K)
   int32_t field_mode;     // FieldMode
   int32_t pad0;
   // mutable state

@@ -302,11 +302,11 @@ __global__ void k_nb_fill(const double* __restrict__ x, const double* __restrict
 // ------------------------------------------------------------ field phase
 // Field of row i at step t (Eq. 2): the dipolar sum of Eq. 3 -- gathered over
 // the neighbours in ascending order with one accumulator per axis, left to
-// right, or carried from earlier steps -- plus H[t] and the thermal draw,
-// projected on the easy and hard axis; then the switching key.  Writes the
-// row's total field and key and returns (key, index | sign bit).  Every
-// field pass (grid-wide or inside a fused workgroup) calls this one
-// function, so they agree bit for bit.
+// right, or carried from earlier steps -- plus H[t], any local external
+// field and the thermal draw, projected on the easy and hard axis; then the
+// switching key.  Writes the row's total field and key and returns (key,
+// index | sign bit).  Every field pass (grid-wide or inside a fused
+// workgroup) calls this one function, so they agree bit for bit.
 __device__ __forceinline__ double field_finish(const InstDev* __restrict__ I, int64_t i, int64_t t,
                                                double p, double pq, uint32_t& payload);
 
@@ -364,8 +364,8 @@ __device__ __forceinline__ double field_row(const InstDev* __restrict__ I, int64
   return field_finish(I, i, t, p, pq, payload);
 }
 
-// Eq. 2 for row i from its dipolar sums (p, pq): plus H[t] and the thermal
-// draw, projected; writes the total field and the key, returns the key.
+// Eq. 2 for row i from its dipolar sums (p, pq): plus H[t], the magnet's
+// local external field (if any) and the thermal draw, projected; writes the total field and the key, returns the key.
 __device__ __forceinline__ double field_finish(const InstDev* __restrict__ I, int64_t i, int64_t t,
                                                double p, double pq, uint32_t& payload) {
   const int8_t* __restrict__ s = I->s;
@@ -375,6 +375,12 @@ __device__ __forceinline__ double field_finish(const InstDev* __restrict__ I, in
     const double Hx = I->H[2 * t], Hy = I->H[2 * t + 1];
     hp = hp + (Hx * mxi + Hy * myi);
     hq = hq + (Hy * mxi - Hx * myi);
+    if (I->hloc) {
+      // the magnet's own external field (Sec. II.D), static or of step t
+      const double2 l = I->hloc[(I->hloc_k > 1 ? t * I->n : 0) + i];
+      hp = hp + (l.x * mxi + l.y * myi);
+      hq = hq + (l.y * mxi - l.x * myi);
+    }
     if (I->sigma > 0.0) {
       double z0, z1;
       thermal_normals(I->seed, (uint32_t)i, (uint32_t)t, z0, z1);

@@ -104,6 +104,7 @@ struct asi_sim {
   int32_t* blk_row0 = nullptr;
   int64_t nblocks = 0;
   double* dH = nullptr;
+  double* dHloc = nullptr;
   int64_t K = 0;
   int64_t cur_step = -1;
   bool poisoned = false;
@@ -539,6 +540,8 @@ asi_status asi_set_field_protocol(asi_handle h, int64_t n_steps, const double* h
   if (st != ASI_OK) return st;
   if (n_steps < 0 || n_steps >= (int64_t)0x7fffffff || (n_steps > 0 && !h_xy))
     return fail(ASI_EINVAL, "bad protocol");
+  if (h->hI.hloc_k > 1 && n_steps != h->hI.hloc_k)
+    return fail(ASI_EINVAL, "protocol length differs from the local field series");
   for (int64_t k = 0; k < 2 * n_steps; ++k)
     if (!std::isfinite(h_xy[k])) return fail(ASI_EINVAL, "non-finite protocol value");
   HIPCHK(hipStreamSynchronize(h->stream), h);
@@ -554,6 +557,29 @@ asi_status asi_set_field_protocol(asi_handle h, int64_t n_steps, const double* h
   h->hI.H = h->dH;
   h->hI.K = n_steps;
   if (h->cur_step >= n_steps) h->cur_step = -1;
+  st = upload_desc(h);
+  if (st != ASI_OK) return st;
+  return sync_and_check(h);
+}
+
+asi_status asi_set_local_field(asi_handle h, int64_t n_slabs, const double* h_loc) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (n_slabs < 0 || (n_slabs > 1 && n_slabs != h->K) || (n_slabs > 0 && !h_loc))
+    return fail(ASI_EINVAL, "bad local field: n_slabs must be 0, 1 or the protocol length");
+  const int64_t cnt = 2 * n_slabs * h->n;
+  for (int64_t k = 0; k < cnt; ++k)
+    if (!std::isfinite(h_loc[k])) return fail(ASI_EINVAL, "non-finite local field value");
+  HIPCHK(hipStreamSynchronize(h->stream), h);
+  if (h->dHloc) h->mem.release(h->dHloc);
+  h->dHloc = nullptr;
+  if (n_slabs > 0) {
+    h->dHloc = dalloc<double>(h, cnt);
+    if (!h->dHloc) return fail(ASI_ENOMEM, "device allocation failed (local field)");
+    HIPCHK(hipMemcpyAsync(h->dHloc, h_loc, 8 * cnt, hipMemcpyHostToDevice, h->stream), h);
+  }
+  h->hI.hloc = reinterpret_cast<const double2*>(h->dHloc);
+  h->hI.hloc_k = n_slabs;
   st = upload_desc(h);
   if (st != ASI_OK) return st;
   return sync_and_check(h);
@@ -837,7 +863,8 @@ asi_status asi_get_info(asi_handle h, asi_info* out) {
   out->max_degree = h->D;
   out->relax_waves = h->relax_waves;
   out->device_bytes = (int64_t)h->mem.total;
-  out->field_pass_bytes = 20.0 * (double)h->E + 53.0 * (double)h->n;
+  out->field_pass_bytes = 20.0 * (double)h->E + 53.0 * (double)h->n +
+                          (h->hI.hloc ? 16.0 * (double)h->n : 0.0);
   out->flip_log_capacity = h->hI.log_cap;
   return ASI_OK;
 }

@@ -4,6 +4,7 @@ Bar: flip sequences (step, magnet) and final spins bit-exact; fields within
 1e-12 of the per-magnet summand scale S_i = alpha*sum_j |g_ij| + |H| + |h_th|
 (cancellation makes |h_i| itself a poor denominator).
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -354,6 +355,128 @@ def test_tuned_instances_batch_bitwise():
     for s, r in zip(sims, refs):
         lg = s.flip_log(cap=0)
         assert (lg["count"], lg["hash"]) == (r["count"], r["hash"])
+
+
+# ------------------------------------------------------------------ local fields (Sec. II.D)
+def _gradient_kagome():
+    xy, theta = W.kagome(16, 15)
+    n = len(theta)
+    H = W.rotating(60, 0.05, 20)
+    return W.Workload("kagome16_gradient", xy, theta, np.ones(n, np.int8),
+                      W.disorder_hk(n, 0.15, 0.05, 21), H, alpha=0.002, neighbor_distance=3.0,
+                      b=0.38, c=1, beta=1.5, gamma=3.9, thermal_std=0.001, thermal_seed=4,
+                      h_loc=W.spatial_gradient(xy, 0.0025, 200.0, 30.0))
+
+
+@pytest.mark.parametrize("mode", ["carry", "dirty", "full"])
+@pytest.mark.parametrize("spec", [False, True])
+def test_static_spatial_field_bit_exact(mode, spec):
+    """A static spatial field (a gradient sampled at the positions) on top
+    of a rotating global field: flips bit-exact against the oracle in every
+    field mode, on the max-tree and on the speculative relax."""
+    w = _gradient_kagome()
+    say("static spatial field", w.n, mode, spec)
+    sim = gpu_sim(w, field_mode=mode)
+    if spec:
+        t = sim.tuning()
+        sim.set_tuning(t["relax_waves"], t["l1_shift"], 1)
+    sim.run()
+    o, r = oracle_run(w)
+    log = sim.flip_log()
+    assert_same_flips(log, r, sim.state()[0], o.spins())
+    assert np.array_equal(sim.step_flips(), r["per_step"])
+    assert_fields_close(o, sim, w.H[-1], w.n_steps - 1)
+    # the field matters: the same run without it switches differently
+    plain = gpu_sim(dataclasses.replace(w, h_loc=None), field_mode=mode)
+    plain.run()
+    assert plain.flip_log(cap=0)["hash"] != log["hash"]
+
+
+@pytest.mark.parametrize("mode", ["carry", "full"])
+def test_travelling_wave_series_bit_exact(mode):
+    """A local field of its own at every step (a wave moving across a
+    pinwheel array, plus thermal noise), against the oracle; then the fields
+    of single steps, which read that step's slab."""
+    xy, theta = W.pinwheel_diamond(22)
+    n = len(theta)
+    K = 48
+    H = W.linear_ramp(K, 0.04, -0.04, 10.0)
+    w = W.Workload("pinwheel22_wave", xy, theta, W.polarised_spins(theta, [0.1, 0.0]),
+                   W.disorder_hk(n, 0.2, 0.05, 23), H, alpha=0.0013, neighbor_distance=4.0,
+                   b=0.38, c=1, beta=1.5, gamma=3.9, thermal_std=0.003, thermal_seed=8,
+                   h_loc=W.travelling_wave(xy, K, 0.09, 9.0, 16, 80.0))
+    say("travelling wave series", n, mode)
+    sim = gpu_sim(w, field_mode=mode)
+    sim.run()
+    o, r = oracle_run(w)
+    assert r["n_flips"] > n
+    assert_same_flips(sim.flip_log(), r, sim.state()[0], o.spins())
+    assert_fields_close(o, sim, w.H[-1], K - 1)
+    for t in (0, 17, K - 1):
+        sim.compute_fields(t)
+        assert_fields_close(o, sim, w.H[t], t)
+
+
+def test_local_field_high_degree_and_updates():
+    """The one-workgroup-per-slice pass (128+ neighbours) adds the local
+    field like the per-lane pass; replacing and removing the field take
+    effect at the next step; a series must match the protocol length."""
+    xy, theta = W.pinwheel_diamond(23)
+    n = len(theta)
+    H = W.linear_ramp(40, 0.08, -0.08, 30.0)
+    w = W.Workload("pinwheel23_d7_local", xy, theta, W.polarised_spins(theta, H[0]),
+                   W.disorder_hk(n, 0.2, 0.05, 11), H, alpha=0.0013, neighbor_distance=7.0,
+                   b=0.38, c=1, beta=1.5, gamma=3.9,
+                   h_loc=W.random_local(n, 1, 0.02, 31))
+    a = gpu_sim(w, field_mode="full")
+    say("local field high degree", n, a.info()["max_degree"])
+    assert a.info()["max_degree"] >= 128
+    a.run(0, 20)
+    o, r = oracle_run(w, 0, 20)
+    assert_same_flips(a.flip_log(), r, a.state()[0], o.spins())
+    # new static field from step 20 on, then none from step 30 on
+    loc2 = W.random_local(n, 1, 0.03, 32)
+    a.set_local_field(loc2)
+    o.set_local_field(loc2)
+    a.run(20, 30)
+    r2 = o.run(w.H, 20, 30)
+    a.set_local_field(None)
+    o.set_local_field(None)
+    a.run(30, 40)
+    r3 = o.run(w.H, 30, 40)
+    log = a.flip_log()
+    steps = np.concatenate([r["step"], r2["step"], r3["step"]])
+    idx = np.concatenate([r["idx"], r2["idx"], r3["idx"]])
+    assert np.array_equal(log["step"], steps) and np.array_equal(log["idx"], idx)
+    assert np.array_equal(a.state()[0], o.spins())
+    with pytest.raises(asi.AsiError):
+        a.set_local_field(W.random_local(n, 7, 0.01, 1))
+    with pytest.raises(asi.AsiError):
+        a.set_local_field(np.full((n, 2), np.nan))
+
+
+def test_local_fields_batch_bitwise():
+    """Instances with static, per-step and no local fields in one fused
+    launch: each bitwise identical to its plain run."""
+    ws = W.batched_sweep(count=6, seed=9, n_steps=50)
+    for k, w in enumerate(ws):
+        if k % 3 == 1:
+            w.h_loc = W.spatial_gradient(w.xy, 0.002, 180.0 + 20 * k, 15.0 * k)
+        elif k % 3 == 2:
+            w.h_loc = W.travelling_wave(w.xy, w.n_steps, 0.05, 7.0, 12, 45.0 * k)
+    refs, sims = [], []
+    for w in ws:
+        r = gpu_sim(w)
+        r.run()
+        refs.append(r.flip_log(cap=0))
+        sims.append(gpu_sim(w))
+    say("local fields batched", [w.n for w in ws])
+    asi.batch_run(sims, mode="fused")
+    for s, r in zip(sims, refs):
+        lg = s.flip_log(cap=0)
+        assert (lg["count"], lg["hash"]) == (r["count"], r["hash"])
+    o, r = oracle_run(ws[5])
+    assert sims[5].flip_log(cap=0)["hash"] == asi.flip_hash(r["step"], r["idx"])
 
 
 # ------------------------------------------------------------------ edge cases
