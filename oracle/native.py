@@ -44,6 +44,7 @@ def lib():
         L.orc_set_spins.argtypes = [P, C.c_void_p]
         L.orc_get_spins.argtypes = [P, C.c_void_p]
         L.orc_set_local_field.argtypes = [P, C.c_int64, C.c_void_p]
+        L.orc_set_thermal_schedule.argtypes = [P, C.c_int64, C.c_void_p]
         L.orc_fields.argtypes = [P, dp, C.c_int64] + [C.c_void_p] * 5
         L.orc_run.restype = C.c_int
         L.orc_run.argtypes = [P, C.c_int64, dp, C.c_int64, C.c_int64, C.c_void_p,
@@ -108,6 +109,8 @@ class Oracle:
         o = cls(w.xy, w.theta, w.hk, **w.params())
         if getattr(w, "h_loc", None) is not None:
             o.set_local_field(w.h_loc)
+        if getattr(w, "sigma_t", None) is not None:
+            o.set_thermal_schedule(w.sigma_t)
         return o
 
     def close(self):
@@ -156,9 +159,16 @@ class Oracle:
         self._loc_k = a.shape[0]
         lib().orc_set_local_field(self._h, a.shape[0], _vp(a))
 
+    def set_thermal_schedule(self, sigma):
+        """Thermal std per step (annealing, Sec. IV.B), or None."""
+        a = np.zeros(0) if sigma is None else np.ascontiguousarray(sigma, dtype=np.float64)
+        self._sig = a
+        lib().orc_set_thermal_schedule(self._h, len(a), _vp(a) if len(a) else None)
+
     def fields(self, H, t):
         """(h_par, h_perp, scale) for the current spins at step t."""
         assert getattr(self, "_loc_k", 0) <= 1 or t < self._loc_k
+        assert len(getattr(self, "_sig", ())) == 0 or t < len(self._sig)
         H = np.ascontiguousarray(H, dtype=np.float64)
         hp, hq, sc = (np.zeros(self.n) for _ in range(3))
         lib().orc_fields(self._h, _dp(H), int(t), _vp(hp), _vp(hq), None, None, _vp(sc))

@@ -27,7 +27,8 @@
 //              recompute fields } until none; then next field step.  The
 //              external and thermal fields are constant during a relax.
 //   Sec. II.E  thermal field: two orthogonal (x, y) components, each
-//              N(0, sigma_th^2), drawn once per magnet per step from
+//              N(0, sigma_th^2) (or N(0, sigma_t[t]^2) under an annealing
+//              schedule, Sec. IV.B), drawn once per magnet per step from
 //              Philox4x32-10 (Salmon et al., SC'11) keyed (seed_lo, seed_hi)
 //              with counter (i, t, 0, 0), mapped by Box-Muller.
 //
@@ -105,6 +106,7 @@ struct Model {
   std::vector<double> gabs;         // alpha * sum_j |g_ij| per row (scale)
   std::vector<int8_t> s;
   std::vector<double> hdx, hdy;     // alpha * sum_j s_j g_ij
+  std::vector<double> sig_t;        // [K] thermal std per step (annealing), or empty
   std::vector<double> loc;          // [loc_k][n][2] local external field
   int64_t loc_k = 0;                // 0 none, 1 static, else one per step
 };
@@ -212,14 +214,16 @@ const double* local_for_step(const Model& M, int64_t t) {
 }
 
 // Step t < 0 is the state before the first field step: no thermal draw.
+// With a schedule, step t uses its own standard deviation sig_t[t].
 void thermal_for_step(const Model& M, int64_t t, StepFields& F) {
-  if (M.sigma_th == 0.0 || t < 0) { F.thx.clear(); F.thy.clear(); return; }
+  const double sigma = (M.sig_t.empty() || t < 0) ? M.sigma_th : M.sig_t[(size_t)t];
+  if (sigma == 0.0 || t < 0) { F.thx.clear(); F.thy.clear(); return; }
   F.thx.resize(M.n); F.thy.resize(M.n);
   for (int64_t i = 0; i < M.n; ++i) {
     double z0, z1;
     normal_pair(M.seed, (uint32_t)i, (uint32_t)t, 0u, &z0, &z1);
-    F.thx[i] = M.sigma_th * z0;
-    F.thy[i] = M.sigma_th * z1;
+    F.thx[i] = sigma * z0;
+    F.thy[i] = sigma * z1;
   }
 }
 
@@ -333,6 +337,13 @@ void orc_set_local_field(void* h, int64_t loc_k, const double* loc) {
   M.loc.assign(loc, loc + (size_t)(2 * loc_k * M.n));
 }
 
+// Thermal schedule (annealing): sigma[t] for steps 0..K-1 replaces sigma_th;
+// K = 0 returns to sigma_th.
+void orc_set_thermal_schedule(void* h, int64_t K, const double* sigma) {
+  Model& M = *static_cast<Model*>(h);
+  M.sig_t.assign(sigma, sigma + (size_t)K);
+}
+
 void orc_get_spins(void* h, int8_t* s) {
   Model& M = *static_cast<Model*>(h);
   std::memcpy(s, M.s.data(), M.n);
@@ -379,7 +390,8 @@ int orc_run(void* h, int64_t K, const double* H, int64_t t_begin, int64_t t_end,
   std::vector<char> in_set(M.n, 0);
   StepFields F;
   for (int64_t t = t_begin; t < t_end && status == 0; ++t) {
-    if (t < 0 || t >= K || (M.loc_k > 1 && t >= M.loc_k)) { status = -1; break; }
+    if (t < 0 || t >= K || (M.loc_k > 1 && t >= M.loc_k) ||
+        (!M.sig_t.empty() && t >= (int64_t)M.sig_t.size())) { status = -1; break; }
     F.Hx = H[2 * t]; F.Hy = H[2 * t + 1];
     F.loc = local_for_step(M, t);
     thermal_for_step(M, t, F);

@@ -151,6 +151,14 @@ def random_local(n: int, n_slabs: int, amp: float, seed: int):
     return np.ascontiguousarray(z[0] if n_slabs == 1 else z)
 
 
+def exponential_anneal(n_steps: int, sigma0: float, sigma1: float):
+    """Thermal std falling exponentially from sigma0 at the first step to
+    sigma1 at the last (Sec. IV.B): sigma0 * (sigma1/sigma0)^(t/(K-1))."""
+    K = int(n_steps)
+    t = np.arange(K, dtype=np.float64) / max(1, K - 1)
+    return np.ascontiguousarray(sigma0 * (sigma1 / sigma0) ** t)
+
+
 # --------------------------------------------------------------------------
 # random inputs
 # --------------------------------------------------------------------------
@@ -199,6 +207,8 @@ class Workload:
     # per-magnet external field added to H (Sec. II.D): [n,2] static or
     # [K,n,2] one slab per step; None for the global field alone
     h_loc: Optional[np.ndarray] = None
+    # thermal std of each step (annealing, Sec. IV.B), replacing thermal_std
+    sigma_t: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:

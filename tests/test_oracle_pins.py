@@ -6,6 +6,7 @@ Stoner-Wohlfarth astroid (Eq. 4 / Eq. 5 special cases), symmetry, an energy
 invariant, the alpha = 0 special case, brute force and published Philox
 known-answer vectors.
 """
+import dataclasses
 import math
 import os
 
@@ -461,3 +462,71 @@ def test_p11_uniform_local_field_equals_global_field(series):
     r_plain = plain.run(w.H)
     assert not (r_plain["n_flips"] == r_glob["n_flips"] and
                 np.array_equal(r_plain["idx"], r_glob["idx"]))
+
+
+# ---------------------------------------------------------------- P12: thermal schedule
+def test_p12_annealing_schedule_on_independent_magnets():
+    """alpha = 0 under an exponentially falling thermal std (Sec. IV.B): each
+    magnet's schedule follows from H[t] + sigma[t] * (z0, z1)(i, t), with the
+    normals of the pinned generator at counter (i, t, 0, 0).  A schedule read
+    at the wrong step, squared, or ignored moves it."""
+    n, K = 50, 60
+    xy, theta = W.random_cloud(n, 17, min_sep=0.4)
+    hk = W.disorder_hk(n, 0.2, 0.05, 17)
+    H = W.rotating(K, 0.02, 13)
+    sig = W.exponential_anneal(K, 0.25, 0.004)
+    b, c, beta, gamma, seed = 0.4, 1.0, 3.0, 3.0, 99
+    o = N.Oracle(**_model(xy, theta, hk, 0.0, 5.0, b, c, beta, gamma, sigma=0.01, seed=seed))
+    spins0 = np.ones(n, dtype=np.int8)
+    o.set_spins(spins0)
+    o.set_thermal_schedule(sig)
+    r = o.run(H)
+    mx, my = np.cos(theta), np.sin(theta)
+    s = spins0.astype(float).copy()
+    expect = []
+    for t in range(K):
+        z = np.array([N.normal_pair(seed, i, t) for i in range(n)])
+        hx = H[t, 0] + sig[t] * z[:, 0]
+        hy = H[t, 1] + sig[t] * z[:, 1]
+        hp = hx * mx + hy * my
+        hq = hy * mx - hx * my
+        L = (np.abs(hp) / (b * hk)) ** (2 / gamma) + (np.abs(hq) / (c * hk)) ** (2 / beta)
+        ok = np.nonzero((s * hp < 0) & (L > 1))[0]
+        for i in sorted(ok, key=lambda i: (-L[i], i)):
+            expect.append((t, i))
+            s[i] = -s[i]
+    got = list(zip(r["step"].tolist(), r["idx"].tolist()))
+    assert got == expect
+    late = [t for t, _ in got if t >= K // 2]
+    assert len(got) > n and len(late) < len(got) // 4   # the noise dies down
+
+
+def test_p12_constant_and_switched_off_schedules():
+    """A constant schedule is the constant thermal_std; steps whose std is 0
+    run as without thermal noise, continuing from the same state."""
+    w = W.square_10x10_triangle()
+    w = dataclasses.replace(w, thermal_std=0.02, thermal_seed=5)
+    ref = N.Oracle.from_workload(w)
+    ref.set_spins(w.spin0)
+    r_ref = ref.run(w.H)
+    o = N.Oracle.from_workload(w)
+    o.set_spins(w.spin0)
+    o.set_thermal_schedule(np.full(w.n_steps, 0.02))
+    r = o.run(w.H)
+    assert np.array_equal(r["idx"], r_ref["idx"]) and np.array_equal(r["step"], r_ref["step"])
+    # noise for the first 60 steps, none after: the tail equals a noiseless
+    # run started from the state after step 59
+    T1 = 60
+    sig = np.where(np.arange(w.n_steps) < T1, 0.02, 0.0)
+    o.set_spins(w.spin0)
+    o.set_thermal_schedule(sig)
+    r1 = o.run(w.H, 0, T1)
+    mid = o.spins()
+    r2 = o.run(w.H, T1, w.n_steps)
+    cold = N.Oracle.from_workload(dataclasses.replace(w, thermal_std=0.0))
+    cold.set_spins(mid)
+    r3 = cold.run(w.H, T1, w.n_steps)
+    assert np.array_equal(r1["idx"], r_ref["idx"][:len(r1["idx"])])
+    assert np.array_equal(r2["idx"], r3["idx"]) and np.array_equal(r2["step"], r3["step"])
+    assert np.array_equal(o.spins(), cold.spins())
+    assert r2["n_flips"] > 0
