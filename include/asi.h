@@ -120,6 +120,15 @@ asi_status asi_set_field_protocol(asi_handle h, int64_t n_steps, const double* h
  * 1) is set, asi_set_field_protocol accepts only the same length. */
 asi_status asi_set_local_field(asi_handle h, int64_t n_slabs, const double* h_loc);
 
+/* Thermal schedule (Sec. II.E; the annealing protocols of Sec. IV.B): step t
+ * draws its thermal field with standard deviation sigma[t] instead of
+ * thermal_std (same normals: Philox counter (i, t, 0, 0)), so a constant
+ * schedule equals that constant thermal_std bit for bit.  n_steps must equal
+ * the protocol length; 0 returns to thermal_std.  Copied; host memory;
+ * ASI_EINVAL for another length, a NULL sigma or a negative or non-finite
+ * value.  While set, asi_set_field_protocol accepts only the same length. */
+asi_status asi_set_thermal_schedule(asi_handle h, int64_t n_steps, const double* sigma);
+
 /* Relax under the current step's fields (Sec. II.H) without advancing t.
  * flips_out (may be NULL) receives the number of flips of this call. */
 asi_status asi_relax(asi_handle h, int64_t* flips_out);

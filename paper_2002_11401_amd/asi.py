@@ -88,6 +88,7 @@ SIGNATURES = {
     "asi_create": [C.POINTER(AsiParams), C.POINTER(AsiDevice), C.POINTER(C.c_void_p)],
     "asi_set_field_protocol": [P, C.c_int64, P],
     "asi_set_local_field": [P, C.c_int64, P],
+    "asi_set_thermal_schedule": [P, C.c_int64, P],
     "asi_relax": [P, I64P],
     "asi_run": [P, C.c_int64, C.c_int64, I64P],
     "asi_get_state": [P, P, P, P, I64P],
@@ -252,6 +253,8 @@ class Sim:
         sim = cls(w.xy, w.theta, w.hk, w.spin0, H=w.H, device=device, **w.params(), **kw)
         if getattr(w, "h_loc", None) is not None:
             sim.set_local_field(w.h_loc)
+        if getattr(w, "sigma_t", None) is not None:
+            sim.set_thermal_schedule(w.sigma_t)
         return sim
 
     @property
@@ -289,6 +292,16 @@ class Sim:
         if a.ndim != 3 or a.shape[1] != self.n or a.shape[2] != 2:
             raise ValueError("h_loc must be (n, 2) or (K, n, 2)")
         _check(library().asi_set_local_field(self.handle, a.shape[0], _ptr(a)))
+
+    def set_thermal_schedule(self, sigma):
+        """Thermal std of every step (length K), or None for thermal_std."""
+        if sigma is None:
+            _check(library().asi_set_thermal_schedule(self.handle, 0, None))
+            return
+        a = np.ascontiguousarray(sigma, dtype=np.float64).reshape(-1)
+        if len(a) != self.K:
+            raise ValueError("the schedule needs one value per protocol step")
+        _check(library().asi_set_thermal_schedule(self.handle, len(a), _ptr(a)))
 
     def run(self, t_begin=0, t_end=None) -> int:
         t_end = self.K if t_end is None else int(t_end)

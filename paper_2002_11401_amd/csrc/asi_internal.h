@@ -53,6 +53,7 @@ struct InstDev {
   double b, c;            // astroid width parameters
   double e_par, e_perp;   // astroid exponents 2/gamma and 2/beta
   double sigma;           // thermal std
+  const double* sigma_t;  // [K] thermal std of each step (replaces sigma), or null
   uint64_t seed;          // thermal Philox key
   const double* H;        // [K][2] applied field per step
   int64_t K;

@@ -381,10 +381,11 @@ __device__ __forceinline__ double field_finish(const InstDev* __restrict__ I, in
       hp = hp + (l.x * mxi + l.y * myi);
       hq = hq + (l.y * mxi - l.x * myi);
     }
-    if (I->sigma > 0.0) {
+    const double sg = I->sigma_t ? I->sigma_t[t] : I->sigma;
+    if (sg > 0.0) {
       double z0, z1;
       thermal_normals(I->seed, (uint32_t)i, (uint32_t)t, z0, z1);
-      const double tx = I->sigma * z0, ty = I->sigma * z1;
+      const double tx = sg * z0, ty = sg * z1;
       hp = hp + (tx * mxi + ty * myi);
       hq = hq + (ty * mxi - tx * myi);
     }

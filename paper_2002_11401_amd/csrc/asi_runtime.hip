@@ -105,6 +105,7 @@ struct asi_sim {
   int64_t nblocks = 0;
   double* dH = nullptr;
   double* dHloc = nullptr;
+  double* dSig = nullptr;
   int64_t K = 0;
   int64_t cur_step = -1;
   bool poisoned = false;
@@ -542,6 +543,8 @@ asi_status asi_set_field_protocol(asi_handle h, int64_t n_steps, const double* h
     return fail(ASI_EINVAL, "bad protocol");
   if (h->hI.hloc_k > 1 && n_steps != h->hI.hloc_k)
     return fail(ASI_EINVAL, "protocol length differs from the local field series");
+  if (h->hI.sigma_t && n_steps != h->K)
+    return fail(ASI_EINVAL, "protocol length differs from the thermal schedule");
   for (int64_t k = 0; k < 2 * n_steps; ++k)
     if (!std::isfinite(h_xy[k])) return fail(ASI_EINVAL, "non-finite protocol value");
   HIPCHK(hipStreamSynchronize(h->stream), h);
@@ -580,6 +583,28 @@ asi_status asi_set_local_field(asi_handle h, int64_t n_slabs, const double* h_lo
   }
   h->hI.hloc = reinterpret_cast<const double2*>(h->dHloc);
   h->hI.hloc_k = n_slabs;
+  st = upload_desc(h);
+  if (st != ASI_OK) return st;
+  return sync_and_check(h);
+}
+
+asi_status asi_set_thermal_schedule(asi_handle h, int64_t n_steps, const double* sigma) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (n_steps < 0 || (n_steps > 0 && (n_steps != h->K || !sigma)))
+    return fail(ASI_EINVAL, "bad thermal schedule: n_steps must be 0 or the protocol length");
+  for (int64_t k = 0; k < n_steps; ++k)
+    if (!(sigma[k] >= 0.0) || !std::isfinite(sigma[k]))
+      return fail(ASI_EINVAL, "thermal schedule values must be finite and >= 0");
+  HIPCHK(hipStreamSynchronize(h->stream), h);
+  if (h->dSig) h->mem.release(h->dSig);
+  h->dSig = nullptr;
+  if (n_steps > 0) {
+    h->dSig = dalloc<double>(h, n_steps);
+    if (!h->dSig) return fail(ASI_ENOMEM, "device allocation failed (thermal schedule)");
+    HIPCHK(hipMemcpyAsync(h->dSig, sigma, 8 * n_steps, hipMemcpyHostToDevice, h->stream), h);
+  }
+  h->hI.sigma_t = h->dSig;
   st = upload_desc(h);
   if (st != ASI_OK) return st;
   return sync_and_check(h);

@@ -272,10 +272,25 @@ def kagome_1m_rotating(n_steps: int = 2000, cells: int = 577) -> Workload:
                     beta=3.0, gamma=3.0, thermal_std=0.005, thermal_seed=2)
 
 
+def square_anneal(side: int = 50, n_steps: int = 200, alpha: float = 0.0015) -> Workload:
+    """Thermal annealing of closed-edge square ASI (Sec. IV.B): b = 0.4,
+    c = 1, beta = gamma = 3, h_k ~ N(0.186, 0.05 * 0.186), neighbourhood 10,
+    no applied field, thermal std falling exponentially 0.12 -> 0.004 over
+    n_steps; all spins +1 at the start."""
+    xy, theta = square_closed(side)
+    n = len(theta)
+    return Workload(f"square{side}_anneal", xy, theta, np.ones(n, np.int8),
+                    disorder_hk(n, 0.186, 0.05, 3), np.zeros((int(n_steps), 2)),
+                    alpha=alpha, neighbor_distance=10.0, b=0.4, c=1.0, beta=3.0, gamma=3.0,
+                    thermal_std=0.0, thermal_seed=12,
+                    sigma_t=exponential_anneal(n_steps, 0.12, 0.004))
+
+
 NAMED = {
     "square10_triangle": square_10x10_triangle,
     "pinwheel100_reversal": pinwheel_100x100_reversal,
     "kagome577_rotating": kagome_1m_rotating,
+    "square50_anneal": square_anneal,
 }
 
 

@@ -56,6 +56,7 @@ def test_invalid_arguments_fail_before_touching_the_device():
     assert lib.asi_get_tuning(None, None) == asi.ASI_EINVAL
     assert lib.asi_set_tuning(None, None) == asi.ASI_EINVAL
     assert lib.asi_set_local_field(None, 1, None) == asi.ASI_EINVAL
+    assert lib.asi_set_thermal_schedule(None, 1, None) == asi.ASI_EINVAL
     assert lib.asi_server_step(None, 1.0, None) == asi.ASI_EINVAL
     assert lib.asi_server_destroy(None) == asi.ASI_OK
 

@@ -479,6 +479,76 @@ def test_local_fields_batch_bitwise():
     assert sims[5].flip_log(cap=0)["hash"] == asi.flip_hash(r["step"], r["idx"])
 
 
+# ------------------------------------------------------------------ annealing (Sec. IV.B)
+@pytest.mark.parametrize("mode,spec", [("carry", False), ("full", False), ("carry", True)])
+def test_annealing_schedule_bit_exact(mode, spec):
+    """Closed square, 10-magnet neighbourhood (631 neighbours), no applied
+    field, thermal std falling exponentially per step: flips bit-exact
+    against the oracle on the tree and the speculative relax, in the
+    carried and the full (one workgroup per slice) field pass."""
+    w = W.square_anneal(side=20, n_steps=100)
+    say("annealing", w.n, mode, spec)
+    sim = gpu_sim(w, field_mode=mode)
+    if spec:
+        t = sim.tuning()
+        sim.set_tuning(t["relax_waves"], t["l1_shift"], 1)
+    sim.run()
+    o, r = oracle_run(w, log_cap=4 * 10 ** 5)
+    assert r["n_flips"] > 4 * w.n
+    log = sim.flip_log()
+    assert_same_flips(log, r, sim.state()[0], o.spins())
+    assert np.array_equal(sim.step_flips(), r["per_step"])
+    assert_fields_close(o, sim, w.H[-1], w.n_steps - 1)
+    for t in (0, 50):
+        sim.compute_fields(t)
+        assert_fields_close(o, sim, w.H[t], t)
+
+
+def test_annealing_schedule_rules_and_batch():
+    """A constant schedule equals thermal_std bit for bit; the schedule must
+    match the protocol length; scheduled instances batch bitwise."""
+    w = W.square_10x10_triangle()
+    a = gpu_sim(dataclasses.replace(w, thermal_std=0.02, thermal_seed=5))
+    b = gpu_sim(dataclasses.replace(w, thermal_std=0.0, thermal_seed=5,
+                                    sigma_t=np.full(w.n_steps, 0.02)))
+    a.run()
+    b.run()
+    assert a.flip_log(cap=0)["hash"] == b.flip_log(cap=0)["hash"]
+    with pytest.raises((asi.AsiError, ValueError)):
+        b.set_thermal_schedule(np.full(w.n_steps - 1, 0.01))
+    with pytest.raises(asi.AsiError):
+        b.set_protocol(w.H[:-1])
+    with pytest.raises(asi.AsiError):
+        b.set_thermal_schedule(np.full(w.n_steps, -0.01))
+    ws = [W.square_anneal(side=s, n_steps=60, alpha=al) for s, al in ((12, 0.001), (16, 0.002),
+                                                                        (20, 0.0015))]
+    ws.append(W.square_10x10_triangle())
+    refs, sims = [], []
+    for x in ws:
+        r = gpu_sim(x)
+        r.run()
+        refs.append(r.flip_log(cap=0))
+        sims.append(gpu_sim(x))
+    say("annealing batched", [x.n for x in ws])
+    asi.batch_run(sims, mode="fused")
+    for s, r in zip(sims, refs):
+        lg = s.flip_log(cap=0)
+        assert (lg["count"], lg["hash"]) == (r["count"], r["hash"])
+
+
+def test_square50_anneal_first_steps():
+    """The 50 x 50 annealing workload (5,100 magnets, 632 neighbours): the
+    first six steps, the busiest of the schedule, against the oracle."""
+    w = W.square_anneal()
+    say("square50 anneal first steps", w.n)
+    sim = gpu_sim(w, field_mode="full")
+    sim.run(0, 6)
+    o, r = oracle_run(w, 0, 6, log_cap=10 ** 5)
+    assert r["n_flips"] > 6000
+    assert_same_flips(sim.flip_log(), r, sim.state()[0], o.spins())
+    assert_fields_close(o, sim, w.H[5], 5)
+
+
 # ------------------------------------------------------------------ edge cases
 def test_single_magnet_and_no_neighbours():
     say("single magnet")
