@@ -22,6 +22,8 @@
 //           h_par = h_i . mhat_i, h_perp = h_i . mhat_perp_i,
 //           mhat_perp_i = (-sin th_i, cos th_i)       (Sec. II.F, Fig. 2)
 //   Eq. 5   L_i = (|h_par|/(b hk_i))^(2/gamma) + (|h_perp|/(c hk_i))^(2/beta)
+//           c = +inf drops the h_perp term; with b = 1, gamma = 2 the test is
+//           then the parallel-only criterion -s_i h_par > hk_i (Sec. IV.C)
 //   Eq. 6   flippable <=> s_i h_par_i < 0  and  L_i > 1
 //   Sec. II.H  repeat { flip argmax_i L_i over flippable (ties: lowest i);
 //              recompute fields } until none; then next field step.  The

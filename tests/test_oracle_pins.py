@@ -530,3 +530,47 @@ def test_p12_constant_and_switched_off_schedules():
     assert np.array_equal(r2["idx"], r3["idx"]) and np.array_equal(r2["step"], r3["step"])
     assert np.array_equal(o.spins(), cold.spins())
     assert r2["n_flips"] > 0
+
+
+# ---------------------------------------------------------------- P13: parallel-only criterion
+PARALLEL = dict(b=1.0, c=math.inf, beta=3.0, gamma=2.0)
+
+
+@pytest.mark.parametrize("hperp_over_hk", [0.0, 0.5, 3.0, 10.0])
+def test_p13_parallel_criterion_single_magnet(hperp_over_hk):
+    """With c = inf, b = 1, gamma = 2 a magnet switches iff the field against
+    its moment exceeds h_k, whatever the hard-axis field (Sec. IV.C); the
+    astroid instead switches under a strong hard-axis field."""
+    hk = 0.2
+    for hpar, expect in ((hk * (1 + 1e-9), 1), (hk * (1 - 1e-9), 0), (0.01 * hk, 0)):
+        H = np.array([[-hpar, hperp_over_hk * hk]])
+        o = N.Oracle(**_model([[0.0, 0.0]], [0.0], [hk], 0.0, 1.0, **PARALLEL))
+        o.set_spins(np.array([1], dtype=np.int8))
+        assert o.run(H)["n_flips"] == expect
+    sw = N.Oracle(**_model([[0.0, 0.0]], [0.0], [hk], 0.0, 1.0))
+    sw.set_spins(np.array([1], dtype=np.int8))
+    assert sw.run(np.array([[-0.01 * hk, 10.0 * hk]]))["n_flips"] == 1
+
+
+def test_p13_parallel_criterion_schedule():
+    """alpha = 0: the schedule under the parallel-only criterion follows from
+    -s_i h_par > h_k alone, ordered by |h_par| / h_k, ties to lower index."""
+    n, K = 60, 50
+    xy, theta = W.random_cloud(n, 21, min_sep=0.4)
+    hk = W.disorder_hk(n, 0.2, 0.05, 21)
+    H = W.linear_ramp(K, 0.3, -0.3, 40.0)
+    spins0 = W.polarised_spins(theta, H[0])
+    o = N.Oracle(**_model(xy, theta, hk, 0.0, 5.0, **PARALLEL))
+    o.set_spins(spins0)
+    r = o.run(H)
+    m = np.stack([np.cos(theta), np.sin(theta)], 1)
+    s = spins0.astype(float).copy()
+    expect = []
+    for t in range(K):
+        hp = m @ H[t]
+        ok = np.nonzero(-s * hp > hk)[0]
+        for i in sorted(ok, key=lambda i: (-abs(hp[i]) / hk[i], i)):
+            expect.append((t, i))
+            s[i] = -s[i]
+    assert list(zip(r["step"].tolist(), r["idx"].tolist())) == expect
+    assert len(expect) >= n // 2
