@@ -74,7 +74,11 @@ typedef struct {
   double alpha;              /* dipolar coupling strength of Eq. 3, finite      */
   double neighbor_distance;  /* d >= 0: j is a neighbour of i iff
                                 (x_i-x_j)^2 + (y_i-y_j)^2 <= (d + 1e-9)^2      */
-  double b, c, beta, gamma;  /* generalized astroid of Eq. 5, all > 0           */
+  double b, c, beta, gamma;  /* generalized astroid of Eq. 5, all > 0; b, beta,
+                                gamma finite.  c may be +INFINITY: the hard-axis
+                                term of Eq. 5 vanishes, and with b = 1, gamma
+                                = 2 the test becomes the parallel-only
+                                criterion -s_i h_par > h_k^(i) (Sec. IV.C)    */
   double thermal_std;        /* sigma_th >= 0 of Sec. II.E; 0 => no thermal     */
   uint64_t thermal_seed;     /* Philox4x32-10 key (lo, hi 32 bits)              */
   int64_t max_flips_per_step;/* 0 => 64 * n; a relax exceeding it => ASI_ELOOP  */

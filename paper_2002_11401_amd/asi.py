@@ -26,6 +26,9 @@ STATUS_NAMES = {0: "ASI_OK", -1: "ASI_EINVAL", -2: "ASI_ENOMEM", -3: "ASI_EDEVIC
 # asi_params.field_mode: carry the dipolar sums across steps by the flip
 # deltas, re-gather rows whose neighbours flipped, or re-gather every row
 FIELD_MODES = {"carry": 0, "dirty": 1, "full": 2}
+# Astroid parameters that reduce Eq. 5 to the parallel-only switching test
+# -s_i h_par > h_k^(i) (Sec. IV.C): no hard-axis term, exponent 1.
+PARALLEL_CRITERION = dict(b=1.0, c=float("inf"), gamma=2.0)
 # asi_batch_run modes
 BATCH_MODES = {"lockstep": 0, "graph": 1, "fused": 2}
 FNV_OFFSET = 0xcbf29ce484222325

@@ -219,8 +219,8 @@ asi_status validate(const asi_params* p) {
   if (!(p->neighbor_distance >= 0.0) || !std::isfinite(p->neighbor_distance))
     return fail(ASI_EINVAL, "neighbor_distance must be finite and >= 0");
   if (!(p->b > 0) || !(p->c > 0) || !(p->beta > 0) || !(p->gamma > 0) || !std::isfinite(p->b) ||
-      !std::isfinite(p->c) || !std::isfinite(p->beta) || !std::isfinite(p->gamma))
-    return fail(ASI_EINVAL, "astroid parameters b, c, beta, gamma must be finite and > 0");
+      std::isnan(p->c) || !std::isfinite(p->beta) || !std::isfinite(p->gamma))
+    return fail(ASI_EINVAL, "astroid parameters b, beta, gamma must be finite and > 0, c > 0");
   if (!(p->thermal_std >= 0.0) || !std::isfinite(p->thermal_std))
     return fail(ASI_EINVAL, "thermal_std must be finite and >= 0");
   if (p->max_flips_per_step < 0 || p->flip_log_capacity < 0)

@@ -58,6 +58,47 @@ def pinwheel_diamond(n_side: int):
     return xy, np.ascontiguousarray(theta + np.pi / 4)
 
 
+def square_open(n_side: int):
+    """Square ASI with open edges: the closed n_side x n_side lattice without
+    its boundary ring of islands (horizontals on rows 1..n-1, verticals on
+    columns 1..n-1), so the outer vertices are left open; 2n(n-1) magnets,
+    horizontals first."""
+    xy, theta = square_closed(n_side)
+    n = int(n_side)
+    keep = np.where(theta == 0.0, (xy[:, 1] > 0) & (xy[:, 1] < n), (xy[:, 0] > 0) & (xy[:, 0] < n))
+    return np.ascontiguousarray(xy[keep]), np.ascontiguousarray(theta[keep])
+
+
+def pinwheel_lucky_knot(n_side: int):
+    """Pinwheel "lucky-knot": the pinwheel lattice (islands turned 45 deg)
+    with the whole lattice turned a further 45 deg, so the array's outline
+    runs along the lattice diagonals; cut to the square of side n_side
+    (lattice units) centred on a vertex.  Islands then lie at 0 and 90 deg.
+    Ordered by y, then x."""
+    n = int(n_side)
+    m = int(math.ceil(n * math.sqrt(2.0))) + 2
+    xy, theta = square_closed(2 * m)
+    xy = xy - float(m)
+    c = math.sqrt(0.5)
+    rot = np.stack([c * xy[:, 0] - c * xy[:, 1], c * xy[:, 0] + c * xy[:, 1]], axis=1)
+    ang = np.mod(theta + np.pi / 2, np.pi)
+    half = n / 2.0
+    keep = (np.abs(rot[:, 0]) <= half) & (np.abs(rot[:, 1]) <= half)
+    rot, ang = rot[keep] + half, ang[keep]
+    order = np.lexsort((rot[:, 0], rot[:, 1]))
+    return np.ascontiguousarray(rot[order]), np.ascontiguousarray(ang[order])
+
+
+def ising(nx: int, ny: Optional[int] = None):
+    """Ising ASI: islands on a square grid of spacing 1, all along x (one
+    sublattice); nx * ny magnets, row-major."""
+    ny = nx if ny is None else ny
+    yy, xx = np.meshgrid(np.arange(int(ny), dtype=np.float64),
+                         np.arange(int(nx), dtype=np.float64), indexing="ij")
+    xy = np.stack([xx.ravel(), yy.ravel()], axis=1)
+    return np.ascontiguousarray(xy), np.zeros(len(xy))
+
+
 def kagome(nu: int, nv: Optional[int] = None):
     """Kagome ASI on nu x nv honeycomb cells (3 islands per cell)."""
     nu = int(nu)

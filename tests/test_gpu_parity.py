@@ -549,6 +549,62 @@ def test_square50_anneal_first_steps():
     assert_fields_close(o, sim, w.H[5], 5)
 
 
+# ------------------------------------------------------------------ parallel-only criterion (Sec. IV.C)
+@pytest.mark.parametrize("spec", [False, True])
+def test_parallel_criterion_pinwheel_reversal(spec):
+    """Pinwheel reversal at 30 deg under the parallel-only switching test
+    (c = inf, b = 1, gamma = 2): flips bit-exact against the oracle on both
+    relax paths, and a different reversal from the astroid's."""
+    xy, theta = W.pinwheel_diamond(30)
+    n = len(theta)
+    H = W.linear_ramp(150, 0.3, -0.3, 30.0)
+    kw = dict(asi.PARALLEL_CRITERION, beta=3.0)
+    w = W.Workload("pinwheel30_parallel", xy, theta, W.polarised_spins(theta, H[0]),
+                   W.disorder_hk(n, 0.2, 0.05, 41), H, alpha=0.0013, neighbor_distance=4.0,
+                   thermal_std=0.002, thermal_seed=3, **kw)
+    say("parallel criterion", n, spec)
+    sim = gpu_sim(w)
+    if spec:
+        t = sim.tuning()
+        sim.set_tuning(t["relax_waves"], t["l1_shift"], 1)
+    sim.run()
+    o, r = oracle_run(w)
+    assert r["n_flips"] >= n // 2   # only the sublattice near the field axis switches
+    log = sim.flip_log()
+    assert_same_flips(log, r, sim.state()[0], o.spins())
+    assert_fields_close(o, sim, w.H[-1], w.n_steps - 1)
+    astroid = gpu_sim(dataclasses.replace(w, b=0.38, c=1.0, beta=1.5, gamma=3.9))
+    astroid.run()
+    assert astroid.flip_log(cap=0)["hash"] != log["hash"]
+
+
+# ------------------------------------------------------------------ more geometries (Fig. 3)
+@pytest.mark.parametrize("geom", ["square_open", "lucky_knot", "ising"])
+def test_more_geometries_bit_exact(geom):
+    """Open-edge square, pinwheel lucky-knot and Ising arrays under a ramp
+    with thermal noise: flips bit-exact against the oracle."""
+    if geom == "square_open":
+        xy, theta = W.square_open(24)
+        H = W.linear_ramp(120, 0.3, -0.3, 42.0)
+    elif geom == "lucky_knot":
+        xy, theta = W.pinwheel_lucky_knot(26)
+        H = W.linear_ramp(120, 0.12, -0.12, 30.0)
+    else:
+        xy, theta = W.ising(40, 33)
+        H = W.rotating(120, 0.2, 60)
+    n = len(theta)
+    w = W.Workload(geom, xy, theta, W.polarised_spins(theta, H[0]),
+                   W.disorder_hk(n, 0.2, 0.05, 51), H, alpha=0.0015, neighbor_distance=3.0,
+                   b=0.38, c=1.0, beta=1.5, gamma=3.9, thermal_std=0.002, thermal_seed=9)
+    say("geometry", geom, n)
+    sim = gpu_sim(w)
+    sim.run()
+    o, r = oracle_run(w)
+    assert r["n_flips"] >= n // 2
+    assert_same_flips(sim.flip_log(), r, sim.state()[0], o.spins())
+    assert_fields_close(o, sim, w.H[-1], w.n_steps - 1)
+
+
 # ------------------------------------------------------------------ edge cases
 def test_single_magnet_and_no_neighbours():
     say("single magnet")

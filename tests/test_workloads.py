@@ -110,3 +110,44 @@ def test_sweep_and_stream_are_reproducible_and_in_range():
                for j in jobs)
     w = jobs[3].workload()
     assert abs(w.n - jobs[3].n_target) / jobs[3].n_target < 0.1
+
+
+def _min_separation(xy):
+    d = np.sqrt(((xy[:, None, :] - xy[None, :, :]) ** 2).sum(-1))
+    np.fill_diagonal(d, np.inf)
+    return d.min()
+
+
+def test_open_square_lucky_knot_and_ising():
+    n = 7
+    xy, theta = W.square_open(n)
+    assert len(theta) == 2 * n * (n - 1)
+    closed, _ = W.square_closed(n)
+    assert {tuple(p) for p in xy} < {tuple(p) for p in closed}
+    # no island on the outer boundary: every vertex of the outline is open
+    assert xy[:, 0].min() > 0 and xy[:, 1].min() > 0 and xy[:, 0].max() < n and xy[:, 1].max() < n
+    xy, theta = W.pinwheel_lucky_knot(12)
+    assert set(np.round(np.degrees(theta)).astype(int)) == {0, 90}
+    assert xy.min() >= 0.0 and xy.max() <= 12.0
+    assert abs(_min_separation(xy) - np.sqrt(0.5)) < 1e-12
+    # the lattice is turned by 45 deg: an island's four nearest neighbours
+    # (the diagonal ones of the square lattice) now lie along the x and y axes
+    i = int(np.argmin(((xy - 6.0) ** 2).sum(1)))
+    d = xy - xy[i]
+    r = np.hypot(d[:, 0], d[:, 1])
+    near = d[(r > 0) & (r < np.sqrt(0.5) + 1e-9)]
+    assert len(near) == 4 and np.allclose(near[:, 0] * near[:, 1], 0.0, atol=1e-15)
+    xy, theta = W.ising(5, 3)
+    assert len(theta) == 15 and not theta.any() and _min_separation(xy) == 1.0
+
+
+def test_local_field_and_schedule_generators():
+    xy, _ = W.kagome(4)
+    g = W.spatial_gradient(xy, 0.01, 90.0, 0.0)
+    assert g.shape == (len(xy), 2) and np.allclose(g[:, 0], 0.0, atol=1e-15)
+    assert abs(g[:, 1].sum()) < 1e-12          # measured from the centre
+    wv = W.travelling_wave(xy, 5, 0.1, 3.0, 4, 0.0)
+    assert wv.shape == (5, len(xy), 2) and np.abs(wv).max() <= 0.1
+    assert np.allclose(wv[4], W.travelling_wave(xy, 1, 0.1, 3.0, 4, 0.0)[0])  # period 4 steps
+    s = W.exponential_anneal(11, 0.2, 0.002)
+    assert s[0] == 0.2 and abs(s[-1] - 0.002) < 1e-15 and np.allclose(s[1:] / s[:-1], 0.01 ** 0.1)
