@@ -133,6 +133,21 @@ asi_status asi_set_local_field(asi_handle h, int64_t n_slabs, const double* h_lo
  * value.  While set, asi_set_field_protocol accepts only the same length. */
 asi_status asi_set_thermal_schedule(asi_handle h, int64_t n_steps, const double* sigma);
 
+/* Net magnetisation of the current spins, M = sum_i s_i mhat_i (Eq. 1
+ * summed; a hysteresis loop plots M . Hhat / M_S with M_S = n, Sec. IV),
+ * reduced on the device in a fixed order: the same spins give the same bits.
+ * m_out: host double[2] (x, y). */
+asi_status asi_magnetization(asi_handle h, double* m_out);
+
+/* Per-step magnetisation log: while enabled, asi_run and asi_relax record M
+ * after the relax of every step t they run into row t of a device array of
+ * the protocol's length (rows of steps not run hold NaN; a new protocol
+ * clears it).  Batched and served runs do not record.  enable = 0 frees it. */
+asi_status asi_set_magnetization_log(asi_handle h, int32_t enable);
+
+/* Copy the log: out = host double[n_steps][2].  ASI_ESTATE when it is off. */
+asi_status asi_get_magnetization_log(asi_handle h, double* out);
+
 /* Relax under the current step's fields (Sec. II.H) without advancing t.
  * flips_out (may be NULL) receives the number of flips of this call. */
 asi_status asi_relax(asi_handle h, int64_t* flips_out);

@@ -165,6 +165,12 @@ class Oracle:
         self._sig = a
         lib().orc_set_thermal_schedule(self._h, len(a), _vp(a) if len(a) else None)
 
+    def magnetization(self, spins=None):
+        """Net magnetisation sum_i s_i mhat_i (Eq. 1 summed over the array),
+        for the current spins or the given ones."""
+        s = (self.spins() if spins is None else np.asarray(spins)).astype(np.float64)
+        return np.array([np.sum(s * np.cos(self.theta)), np.sum(s * np.sin(self.theta))])
+
     def fields(self, H, t):
         """(h_par, h_perp, scale) for the current spins at step t."""
         assert getattr(self, "_loc_k", 0) <= 1 or t < self._loc_k

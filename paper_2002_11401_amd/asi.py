@@ -92,6 +92,9 @@ SIGNATURES = {
     "asi_set_field_protocol": [P, C.c_int64, P],
     "asi_set_local_field": [P, C.c_int64, P],
     "asi_set_thermal_schedule": [P, C.c_int64, P],
+    "asi_magnetization": [P, P],
+    "asi_set_magnetization_log": [P, C.c_int32],
+    "asi_get_magnetization_log": [P, P],
     "asi_relax": [P, I64P],
     "asi_run": [P, C.c_int64, C.c_int64, I64P],
     "asi_get_state": [P, P, P, P, I64P],
@@ -305,6 +308,22 @@ class Sim:
         if len(a) != self.K:
             raise ValueError("the schedule needs one value per protocol step")
         _check(library().asi_set_thermal_schedule(self.handle, len(a), _ptr(a)))
+
+    def magnetization(self) -> np.ndarray:
+        """Net magnetisation sum_i s_i mhat_i of the current spins, (x, y)."""
+        m = np.zeros(2)
+        _check(library().asi_magnetization(self.handle, _ptr(m)))
+        return m
+
+    def set_magnetization_log(self, on: bool = True):
+        _check(library().asi_set_magnetization_log(self.handle, 1 if on else 0))
+
+    def magnetization_log(self) -> np.ndarray:
+        """[K, 2]: M after the relax of each step run since the log was
+        enabled (NaN for steps not run)."""
+        out = np.zeros((max(1, self.K), 2))
+        _check(library().asi_get_magnetization_log(self.handle, _ptr(out)))
+        return out[:self.K]
 
     def run(self, t_begin=0, t_end=None) -> int:
         t_end = self.K if t_end is None else int(t_end)

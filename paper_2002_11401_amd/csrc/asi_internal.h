@@ -110,6 +110,11 @@ struct RunDev {
 
 // Coercive fields drawn from the disorder distribution (asi_params.hk == NULL).
 void launch_draw_hk(double* hk, int64_t n, double mean, double k, uint64_t seed, hipStream_t st);
+// Net magnetisation sum_i s_i mhat_i of n magnets into out[2]; part holds
+// kMagPartials doubles of block sums.  Fixed reduction order.
+constexpr int kMagPartials = 2 * 256;
+void launch_magnetization(const int8_t* s, const double* mx, const double* my, int64_t n,
+                          double* part, double* out, hipStream_t st);
 void launch_neighbour_count(const double* x, const double* y, const int32_t* cellx,
                             const int32_t* celly, const int32_t* cell_start,
                             const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,

@@ -1933,9 +1933,71 @@ __global__ void k_set_run(RunDev* R, int64_t t, int64_t t_end, int32_t active,
   }
 }
 
+// ------------------------------------------------------------ analysis
+// Net magnetisation M = sum_i s_i mhat_i, the quantity a hysteresis loop
+// plots (as M / M_S, M_S = n for unit moments).  Reduced in a fixed order,
+// so the same spins give the same bits on every call: thread k of block b
+// adds rows b*T + k, then every G*T rows, in ascending order; the block
+// halves its sums in LDS; one block then halves the G block sums.
+constexpr int kMagThreads = 256;
+constexpr int kMagBlocks = 256;   // == kMagThreads: the final block takes one sum per thread
+
+__device__ __forceinline__ void mag_halve(double* sx, double* sy) {
+  for (int w = kMagThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sx[threadIdx.x] = sx[threadIdx.x] + sx[threadIdx.x + w];
+      sy[threadIdx.x] = sy[threadIdx.x] + sy[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kMagThreads)
+k_mag_partial(const int8_t* __restrict__ s, const double* __restrict__ mx,
+              const double* __restrict__ my, int64_t n, double* __restrict__ part) {
+  __shared__ double sx[kMagThreads], sy[kMagThreads];
+  const int64_t stride = (int64_t)kMagBlocks * kMagThreads;
+  double ax = 0.0, ay = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kMagThreads + threadIdx.x; i < n; i += stride) {
+    const bool up = s[i] > 0;
+    ax = ax + (up ? mx[i] : -mx[i]);
+    ay = ay + (up ? my[i] : -my[i]);
+  }
+  sx[threadIdx.x] = ax;
+  sy[threadIdx.x] = ay;
+  __syncthreads();
+  mag_halve(sx, sy);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sx[0];
+    part[2 * blockIdx.x + 1] = sy[0];
+  }
+}
+
+__global__ void __launch_bounds__(kMagThreads)
+k_mag_final(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sx[kMagThreads], sy[kMagThreads];
+  sx[threadIdx.x] = part[2 * threadIdx.x];
+  sy[threadIdx.x] = part[2 * threadIdx.x + 1];
+  __syncthreads();
+  mag_halve(sx, sy);
+  if (threadIdx.x == 0) {
+    out[0] = sx[0];
+    out[1] = sy[0];
+  }
+}
+
+static_assert(2 * kMagBlocks == kMagPartials, "block sums buffer");
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
+void launch_magnetization(const int8_t* s, const double* mx, const double* my, int64_t n,
+                          double* part, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mag_partial, dim3(kMagBlocks), dim3(kMagThreads), 0, st, s, mx, my, n,
+                     part);
+  hipLaunchKernelGGL(k_mag_final, dim3(1), dim3(kMagThreads), 0, st, part, out);
+}
+
 void launch_draw_hk(double* hk, int64_t n, double mean, double k, uint64_t seed, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_draw_hk, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, hk, n, mean, k,

@@ -106,6 +106,9 @@ struct asi_sim {
   double* dH = nullptr;
   double* dHloc = nullptr;
   double* dSig = nullptr;
+  double* dMpart = nullptr;   // [kMagPartials + 2] block sums, then the last result
+  double* dMlog = nullptr;    // [K][2] magnetisation after each step's relax
+  bool mag_log = false;
   int64_t K = 0;
   int64_t cur_step = -1;
   bool poisoned = false;
@@ -493,11 +496,33 @@ asi_status read_run(asi_sim* s, RunDev* r) {
 }
 
 // steps [t0, t1) of the protocol (t0 may be -1 for the zero-field step)
+asi_status ensure_mag_partials(asi_sim* s) {
+  if (s->dMpart) return ASI_OK;
+  s->dMpart = dalloc<double>(s, kMagPartials + 2);
+  if (!s->dMpart) return fail(ASI_ENOMEM, "device allocation failed (magnetisation)");
+  return ASI_OK;
+}
+
+// Per-step magnetisation log of the current protocol length, rows NaN until
+// their step runs.
+asi_status alloc_mag_log(asi_sim* s) {
+  const int64_t cnt = 2 * std::max<int64_t>(1, s->K);
+  s->dMlog = dalloc<double>(s, cnt);
+  if (!s->dMlog) return fail(ASI_ENOMEM, "device allocation failed (magnetisation log)");
+  std::vector<double> nan(cnt, std::nan(""));
+  HIPCHK(hipMemcpyAsync(s->dMlog, nan.data(), 8 * cnt, hipMemcpyHostToDevice, s->stream), s);
+  HIPCHK(hipStreamSynchronize(s->stream), s);
+  return ASI_OK;
+}
+
 asi_status run_steps(asi_sim* s, int64_t t0, int64_t t1, int64_t* flips_out) {
   launch_set_run(s->dR, t0, t1, t0 < t1 ? 1 : 0, 0, 0, s->stream);
   for (int64_t t = t0; t < t1; ++t) {
     field_pass(s);
     relax_pass(s);
+    if (s->mag_log && t >= 0)
+      launch_magnetization(s->hI.s, s->hI.mx, s->hI.my, s->n, s->dMpart, s->dMlog + 2 * t,
+                           s->stream);
   }
   RunDev r{};
   asi_status st = read_run(s, &r);
@@ -559,6 +584,15 @@ asi_status asi_set_field_protocol(asi_handle h, int64_t n_steps, const double* h
   h->K = n_steps;
   h->hI.H = h->dH;
   h->hI.K = n_steps;
+  if (h->mag_log) {
+    if (h->dMlog) h->mem.release(h->dMlog);
+    h->dMlog = nullptr;
+    st = alloc_mag_log(h);
+    if (st != ASI_OK) {
+      h->mag_log = false;
+      return st;
+    }
+  }
   if (h->cur_step >= n_steps) h->cur_step = -1;
   st = upload_desc(h);
   if (st != ASI_OK) return st;
@@ -607,6 +641,44 @@ asi_status asi_set_thermal_schedule(asi_handle h, int64_t n_steps, const double*
   h->hI.sigma_t = h->dSig;
   st = upload_desc(h);
   if (st != ASI_OK) return st;
+  return sync_and_check(h);
+}
+
+asi_status asi_magnetization(asi_handle h, double* m_out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (!m_out) return fail(ASI_EINVAL, "m_out is NULL");
+  st = ensure_mag_partials(h);
+  if (st != ASI_OK) return st;
+  launch_magnetization(h->hI.s, h->hI.mx, h->hI.my, h->n, h->dMpart, h->dMpart + kMagPartials,
+                       h->stream);
+  HIPCHK(hipMemcpyAsync(m_out, h->dMpart + kMagPartials, 16, hipMemcpyDeviceToHost, h->stream), h);
+  return sync_and_check(h);
+}
+
+asi_status asi_set_magnetization_log(asi_handle h, int32_t enable) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  HIPCHK(hipStreamSynchronize(h->stream), h);
+  if (h->dMlog) h->mem.release(h->dMlog);
+  h->dMlog = nullptr;
+  h->mag_log = false;
+  if (!enable) return ASI_OK;
+  st = ensure_mag_partials(h);
+  if (st != ASI_OK) return st;
+  st = alloc_mag_log(h);
+  if (st != ASI_OK) return st;
+  h->mag_log = true;
+  return sync_and_check(h);
+}
+
+asi_status asi_get_magnetization_log(asi_handle h, double* out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (!out) return fail(ASI_EINVAL, "out is NULL");
+  if (!h->mag_log) return fail(ASI_ESTATE, "the magnetisation log is off");
+  if (h->K > 0)
+    HIPCHK(hipMemcpyAsync(out, h->dMlog, 16 * h->K, hipMemcpyDeviceToHost, h->stream), h);
   return sync_and_check(h);
 }
 

@@ -605,6 +605,72 @@ def test_more_geometries_bit_exact(geom):
     assert_fields_close(o, sim, w.H[-1], w.n_steps - 1)
 
 
+# ------------------------------------------------------------------ magnetisation (hysteresis)
+MAG_TOL = 1e-13   # per magnet: two FP64 sums of n unit-bounded terms in different orders
+
+
+def test_magnetisation_of_random_states():
+    """asi_magnetization against the oracle's plain sum for random states on
+    a 1M-magnet kagome, a ragged 1,005-magnet cloud and one magnet; the same
+    spins give the same bits on every call."""
+    cases = [W.kagome_1m_rotating(n_steps=2)]
+    xy, theta = W.random_cloud(1005, 77, min_sep=0.4)
+    cases.append(W.Workload("cloud1005", xy, theta, np.ones(1005, np.int8),
+                            np.full(1005, 0.2), np.zeros((2, 2)), alpha=0.001,
+                            neighbor_distance=1.0, b=1, c=1, beta=3, gamma=3))
+    cases.append(W.Workload("one", np.zeros((1, 2)), np.array([0.7]), np.ones(1, np.int8),
+                            np.array([0.2]), np.zeros((2, 2)), alpha=0.001, neighbor_distance=1.0,
+                            b=1, c=1, beta=3, gamma=3))
+    rng = np.random.default_rng(8)
+    for w in cases:
+        say("magnetisation", w.name, w.n)
+        sim = gpu_sim(w)
+        o = N.Oracle.from_workload(w) if w.n < 10 ** 5 else None
+        for _ in range(3):
+            s = rng.choice([-1, 1], w.n).astype(np.int8)
+            sim.set_state(s, -1)
+            m1 = sim.magnetization()
+            m2 = sim.magnetization()
+            assert m1.tobytes() == m2.tobytes()
+            if o is not None:
+                ref = o.magnetization(s)
+            else:
+                sv = s.astype(np.float64)
+                ref = np.array([np.sum(sv * np.cos(w.theta)), np.sum(sv * np.sin(w.theta))])
+            assert np.all(np.abs(m1 - ref) <= MAG_TOL * w.n), (m1, ref)
+        sim.close()
+
+
+def test_magnetisation_log_follows_the_flip_log():
+    """The per-step log of a reversal with thermal noise equals the
+    magnetisation rebuilt from the oracle's flips step by step; a hysteresis
+    loop of a square array, saturating at both ends."""
+    w = W.square_10x10_triangle()
+    w = dataclasses.replace(w, thermal_std=0.01, thermal_seed=4)
+    say("magnetisation log", w.n)
+    sim = gpu_sim(w)
+    sim.set_magnetization_log(True)
+    assert np.isnan(sim.magnetization_log()).all()
+    sim.run(0, 120)
+    sim.run(120, w.n_steps)
+    log = sim.magnetization_log()
+    o, r = oracle_run(w)
+    assert_same_flips(sim.flip_log(), r, sim.state()[0], o.spins())
+    s = w.spin0.astype(np.int8).copy()
+    k = 0
+    for t in range(w.n_steps):
+        while k < len(r["step"]) and r["step"][k] == t:
+            s[r["idx"][k]] = -s[r["idx"][k]]
+            k += 1
+        assert np.all(np.abs(log[t] - o.magnetization(s)) <= MAG_TOL * w.n), t
+    assert log[-1].tobytes() == sim.magnetization().tobytes()
+    u = np.array([np.sqrt(0.5), np.sqrt(0.5)])
+    proj = log @ u / np.sum(np.abs(np.cos(w.theta - np.pi / 4)))
+    assert proj.min() < -0.99 and proj[-1] > 0.99
+    with pytest.raises(asi.AsiError):
+        gpu_sim(w).magnetization_log()
+
+
 # ------------------------------------------------------------------ edge cases
 def test_single_magnet_and_no_neighbours():
     say("single magnet")

@@ -574,3 +574,40 @@ def test_p13_parallel_criterion_schedule():
             s[i] = -s[i]
     assert list(zip(r["step"].tolist(), r["idx"].tolist())) == expect
     assert len(expect) >= n // 2
+
+
+# ---------------------------------------------------------------- P14: magnetisation
+def test_p14_magnetisation_closed_forms_and_hysteresis():
+    """Net magnetisation: all-up closed square N x N gives (N(N+1), N(N+1));
+    an all-up kagome cell (islands at 90, 30, 150 deg) gives (0, 2) per cell;
+    reversing every spin negates M.  Under a saturating triangle sweep with
+    alpha = 0 the projection on the field axis runs from +M_S to -M_S and
+    back, and the loop is not closed at zero field (hysteresis)."""
+    N_ = 6
+    xy, theta = W.square_closed(N_)
+    o = N.Oracle(**_model(xy, theta, np.full(len(theta), 0.2), 0.0, 1.0))
+    o.set_spins(np.ones(len(theta), np.int8))
+    np.testing.assert_allclose(o.magnetization(), [N_ * (N_ + 1)] * 2, rtol=1e-14)
+    np.testing.assert_allclose(o.magnetization(-np.ones(len(theta), np.int8)),
+                               [-N_ * (N_ + 1)] * 2, rtol=1e-14)
+    xy, theta = W.kagome(3, 2)
+    o = N.Oracle(**_model(xy, theta, np.full(len(theta), 0.2), 0.0, 1.0))
+    o.set_spins(np.ones(len(theta), np.int8))
+    np.testing.assert_allclose(o.magnetization(), [0.0, 2.0 * 6], atol=1e-13)
+    # hysteresis of independent square-lattice magnets at 45 deg
+    xy, theta = W.square_closed(5)
+    n = len(theta)
+    H = W.triangle_ramp(40, 0.4, 45.0)
+    o = N.Oracle(**_model(xy, theta, W.disorder_hk(n, 0.2, 0.05, 3), 0.0, 1.0))
+    o.set_spins(np.ones(n, np.int8))
+    u = np.array([np.sqrt(0.5), np.sqrt(0.5)])
+    ms = np.sum(np.abs(np.cos(theta - np.pi / 4)))   # saturation along the field axis
+    proj = []
+    for t in range(len(H)):
+        o.run(H, t, t + 1)
+        proj.append(o.magnetization() @ u / ms)
+    proj = np.array(proj)
+    assert proj[0] == pytest.approx(1.0) and proj[39] == pytest.approx(-1.0)
+    assert proj[-1] == pytest.approx(1.0)
+    # at the zero crossings of the field the two branches differ
+    assert proj[19] > 0.9 and proj[59] < -0.9
