@@ -98,6 +98,7 @@ class Oracle:
         self.theta = np.ascontiguousarray(theta, dtype=np.float64)
         self.hk = np.ascontiguousarray(hk, dtype=np.float64)
         self.n = len(self.theta)
+        self.alpha = float(alpha)
         self._h = lib().orc_create(self.n, _dp(self.xy), _dp(self.theta), _dp(self.hk),
                                    alpha, neighbor_distance, b, c, beta, gamma,
                                    thermal_std, int(thermal_seed))
@@ -170,6 +171,37 @@ class Oracle:
         for the current spins or the given ones."""
         s = (self.spins() if spins is None else np.asarray(spins)).astype(np.float64)
         return np.array([np.sum(s * np.cos(self.theta)), np.sum(s * np.sin(self.theta))])
+
+    def spin_correlation(self, bin_width, n_bins, spins=None):
+        """(sums, counts) per distance bin of the pair correlation (Sec.
+        IV.B): +1 when the pair's dipolar energy -s_i s_j A_ij is minimal,
+        -1 when maximal, 0 when A_ij vanishes (|A_ij| <= 1e-9 |alpha| / r^3),
+        A_ij = alpha mhat_i . (3 r (mhat_j . r) / |r|^5 - mhat_j / |r|^3)
+        from Eq. 3 with r = r_i - r_j; each neighbour pair once, in bin
+        floor(r / w)."""
+        s = self.spins() if spins is None else np.asarray(spins, dtype=np.int64)
+        ptr, idx = self.neighbours()
+        sums = np.zeros(int(n_bins), dtype=np.int64)
+        cnts = np.zeros(int(n_bins), dtype=np.int64)
+        m = np.stack([np.cos(self.theta), np.sin(self.theta)], 1)
+        for i in range(self.n):
+            js = idx[ptr[i]:ptr[i + 1]]
+            js = js[js > i]
+            if len(js) == 0:
+                continue
+            d = self.xy[i] - self.xy[js]
+            r = np.sqrt(d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1])
+            b = np.floor(r / bin_width)
+            mj = m[js]
+            proj = (mj * d).sum(1)
+            g = 3.0 * d * (proj / r ** 5)[:, None] - mj / (r ** 3)[:, None]
+            A = self.alpha * (g @ m[i])
+            c = np.where(np.abs(A) > 1e-9 * abs(self.alpha) / r ** 3,
+                         np.where(int(s[i]) * s[js] * np.sign(A) > 0, 1, -1), 0)
+            ok = b < n_bins
+            np.add.at(sums, b[ok].astype(np.int64), c[ok])
+            np.add.at(cnts, b[ok].astype(np.int64), 1)
+        return sums, cnts
 
     def fields(self, H, t):
         """(h_par, h_perp, scale) for the current spins at step t."""

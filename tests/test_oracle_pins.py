@@ -611,3 +611,46 @@ def test_p14_magnetisation_closed_forms_and_hysteresis():
     assert proj[-1] == pytest.approx(1.0)
     # at the zero crossings of the field the two branches differ
     assert proj[19] > 0.9 and proj[59] < -0.9
+
+
+# ---------------------------------------------------------------- P15: spin-spin correlation
+def test_p15_pair_correlation_closed_forms():
+    """Two magnets: head-to-tail along their axis the dipolar energy is
+    lowest for parallel moments (correlation +1), side by side for
+    antiparallel ones (-1 when parallel); perpendicular islands with the
+    offset along one of them have no coupling (0).  The pair lands in bin
+    floor(r / w); reversing both spins changes nothing."""
+    alpha = 0.01
+    cases = [([[0, 0], [1.5, 0]], [0, 0], (+1, -1)),       # head-to-tail
+             ([[0, 0], [0, 1.5]], [0, 0], (-1, +1)),       # side by side
+             ([[0, 0], [0, 1.5]], [0, np.pi / 2], (0, 0))]  # perpendicular, zero coupling
+    for xy, th, (par, anti) in cases:
+        o = N.Oracle(**_model(xy, th, [0.2, 0.2], alpha, 2.0))
+        for s, expect in (([1, 1], par), ([1, -1], anti), ([-1, -1], par)):
+            sums, cnts = o.spin_correlation(0.5, 8, np.array(s))
+            assert cnts.tolist() == [0, 0, 0, 1, 0, 0, 0, 0]
+            assert sums[3] == expect
+        sums, cnts = o.spin_correlation(0.5, 3, np.array([1, 1]))
+        assert cnts.sum() == 0                              # past the last bin
+
+
+def test_p15_correlation_of_square_ground_state_vertex_pairs():
+    """Closed square lattice in the type-I ground state (at vertices with x+y
+    even both horizontal islands point in and both vertical ones out, the
+    reverse at odd vertices): every nearest pair (perpendicular islands at a
+    vertex, r = 1/sqrt 2) is at its energy minimum, so that bin averages +1;
+    in the uniform state some of those pairs are frustrated."""
+    n = 6
+    xy, theta = W.square_closed(n)
+    o = N.Oracle(**_model(xy, theta, np.full(len(theta), 0.2), 0.01, 1.0))
+    horiz = theta == 0.0
+    vx = np.where(horiz, np.floor(xy[:, 0]), np.round(xy[:, 0]))
+    vy = np.where(horiz, np.round(xy[:, 1]), np.floor(xy[:, 1]))
+    even = (vx + vy) % 2 == 0
+    s = np.where(horiz, np.where(even, -1, 1), np.where(even, 1, -1)).astype(np.int8)
+    w = 0.1
+    sums, cnts = o.spin_correlation(w, 11, s)
+    b_nn = int(np.floor(np.sqrt(0.5) / w))
+    assert cnts[b_nn] == 4 * n * n and sums[b_nn] == cnts[b_nn]
+    su, cu = o.spin_correlation(w, 11, np.ones(len(theta), np.int8))
+    assert cu[b_nn] == cnts[b_nn] and su[b_nn] < cu[b_nn]
