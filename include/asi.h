@@ -139,6 +139,20 @@ asi_status asi_set_thermal_schedule(asi_handle h, int64_t n_steps, const double*
  * m_out: host double[2] (x, y). */
 asi_status asi_magnetization(asi_handle h, double* m_out);
 
+/* Spin-spin correlation by separation (Sec. IV.B), over the neighbour pairs
+ * of the instance (Sec. II.C), each pair once.  A pair correlates +1 when its
+ * dipolar energy -s_i s_j A_ij is minimal (s_i s_j A_ij > 0, A_ij the
+ * coupling along the easy axes), -1 when maximal, 0 when the coupling is
+ * zero up to rounding (|A_ij| <= 1e-9 |alpha| / r^3).  Pair (i, j) at
+ * distance r = sqrt(dx^2 + dy^2) (each operation correctly rounded, dx =
+ * x_i - x_j) goes to bin floor(r / bin_width) when that is < n_bins.
+ * xy: host [2n], the positions the instance was created with.  Outputs (host
+ * int64[n_bins]): sum_out the summed correlations, count_out the pairs; the
+ * mean correlation of bin b is sum_out[b] / count_out[b].  1 <= n_bins <=
+ * 4096; bin_width finite > 0. */
+asi_status asi_spin_correlation(asi_handle h, const double* xy, double bin_width,
+                                int32_t n_bins, int64_t* sum_out, int64_t* count_out);
+
 /* Per-step magnetisation log: while enabled, asi_run and asi_relax record M
  * after the relax of every step t they run into row t of a device array of
  * the protocol's length (rows of steps not run hold NaN; a new protocol

@@ -93,6 +93,7 @@ SIGNATURES = {
     "asi_set_local_field": [P, C.c_int64, P],
     "asi_set_thermal_schedule": [P, C.c_int64, P],
     "asi_magnetization": [P, P],
+    "asi_spin_correlation": [P, P, C.c_double, C.c_int32, P, P],
     "asi_set_magnetization_log": [P, C.c_int32],
     "asi_get_magnetization_log": [P, P],
     "asi_relax": [P, I64P],
@@ -314,6 +315,18 @@ class Sim:
         m = np.zeros(2)
         _check(library().asi_magnetization(self.handle, _ptr(m)))
         return m
+
+    def spin_correlation(self, xy, bin_width: float, n_bins: int):
+        """(sums, counts) of the pair correlation per distance bin over the
+        neighbour pairs; xy are the instance's positions."""
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        if len(xy) != self.n:
+            raise ValueError("xy must hold the n positions")
+        s = np.zeros(int(n_bins), dtype=np.int64)
+        c = np.zeros(int(n_bins), dtype=np.int64)
+        _check(library().asi_spin_correlation(self.handle, _ptr(xy), float(bin_width),
+                                              int(n_bins), _ptr(s), _ptr(c)))
+        return s, c
 
     def set_magnetization_log(self, on: bool = True):
         _check(library().asi_set_magnetization_log(self.handle, 1 if on else 0))

@@ -115,6 +115,12 @@ void launch_draw_hk(double* hk, int64_t n, double mean, double k, uint64_t seed,
 constexpr int kMagPartials = 2 * 256;
 void launch_magnetization(const int8_t* s, const double* mx, const double* my, int64_t n,
                           double* part, double* out, hipStream_t st);
+// Spin-spin correlation sums and pair counts per distance bin (two's
+// complement sums) over the instance's neighbour pairs; xy is on the device.
+constexpr int kCorrMaxBins = 4096;
+void launch_correlation(const InstDev* inst, int64_t n, const double* xy, double w,
+                        int32_t nbins, double abs_alpha, uint64_t* sum, uint64_t* cnt,
+                        hipStream_t st);
 void launch_neighbour_count(const double* x, const double* y, const int32_t* cellx,
                             const int32_t* celly, const int32_t* cell_start,
                             const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,

@@ -18,6 +18,7 @@
 //                           until none can flip (Sec. II.H)
 //   k_fused                 one workgroup per instance runs whole steps
 //                           (field phase + relax) through its own protocol
+#include <algorithm>
 #include <climits>
 
 #include "asi_internal.h"
@@ -1988,9 +1989,67 @@ k_mag_final(const double* __restrict__ part, double* __restrict__ out) {
 
 static_assert(2 * kMagBlocks == kMagPartials, "block sums buffer");
 
+// Spin-spin correlation by separation (Sec. IV.B): a pair (i, j) of
+// neighbours correlates +1 when its dipolar energy -s_i s_j A_ij is at its
+// minimum (s_i s_j A_ij > 0), -1 at its maximum, and 0 when the coupling
+// vanishes (|A_ij| <= 1e-9 |alpha| / r^3, i.e. zero up to rounding).  Each
+// pair counts once (j > i) in bin floor(r / w) of its distance r; pairs past
+// the last bin are skipped.  The distance is formed with correctly rounded
+// operations only, so the bin is the same as any IEEE evaluation of the
+// same expression.  Sums and counts are integers, added per workgroup in
+// LDS and then once per bin into the global totals.
+__global__ void __launch_bounds__(256)
+k_corr(const InstDev* __restrict__ I, const double* __restrict__ xy, double w, int32_t nbins,
+       double abs_alpha, unsigned long long* __restrict__ sum, unsigned long long* __restrict__ cnt) {
+  extern __shared__ int32_t lds_bins[];   // [2][nbins]
+  int32_t* bs = lds_bins;
+  int32_t* bc = lds_bins + nbins;
+  for (int b = threadIdx.x; b < 2 * nbins; b += blockDim.x) lds_bins[b] = 0;
+  __syncthreads();
+  const int64_t n = I->n, D = I->D;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double xi = xy[2 * i], yi = xy[2 * i + 1];
+    const int si = I->s[i];
+    for (int64_t k = 0; k < D; ++k) {
+      const int32_t j = I->rcol[i * D + k];
+      if (j < 0) break;
+      if (j <= i) continue;
+      const double dx = __dsub_rn(xi, xy[2 * (int64_t)j]);
+      const double dy = __dsub_rn(yi, xy[2 * (int64_t)j + 1]);
+      const double r = __dsqrt_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)));
+      const double q = floor(__ddiv_rn(r, w));
+      if (!(q < (double)nbins)) continue;
+      const int b = (int)q;
+      const double a = I->rA[i * D + k];
+      int c = 0;
+      if (fabs(a) > 1e-9 * abs_alpha / (r * r * r)) c = ((si * I->s[j]) * (a > 0.0 ? 1 : -1) > 0) ? 1 : -1;
+      atomicAdd(&bs[b], c);
+      atomicAdd(&bc[b], 1);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+    if (bc[b] != 0) {
+      atomicAdd(&sum[b], (unsigned long long)(long long)bs[b]);
+      atomicAdd(&cnt[b], (unsigned long long)bc[b]);
+    }
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
+void launch_correlation(const InstDev* inst, int64_t n, const double* xy, double w,
+                        int32_t nbins, double abs_alpha, uint64_t* sum, uint64_t* cnt,
+                        hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(k_corr, dim3((unsigned)blocks), dim3(256), 2 * nbins * sizeof(int32_t), st,
+                     inst, xy, w, nbins, abs_alpha,
+                     reinterpret_cast<unsigned long long*>(sum),
+                     reinterpret_cast<unsigned long long*>(cnt));
+}
+
 void launch_magnetization(const int8_t* s, const double* mx, const double* my, int64_t n,
                           double* part, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_mag_partial, dim3(kMagBlocks), dim3(kMagThreads), 0, st, s, mx, my, n,

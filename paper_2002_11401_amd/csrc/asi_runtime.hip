@@ -106,6 +106,7 @@ struct asi_sim {
   double* dH = nullptr;
   double* dHloc = nullptr;
   double* dSig = nullptr;
+  double alpha = 0.0;
   double* dMpart = nullptr;   // [kMagPartials + 2] block sums, then the last result
   double* dMlog = nullptr;    // [K][2] magnetisation after each step's relax
   bool mag_log = false;
@@ -277,6 +278,7 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   s->mem.st = s->stream;
   const int64_t n = p->n;
   s->n = n;
+  s->alpha = p->alpha;
 
   // host: unit vectors (libm), cell grid and the cell sort
   std::vector<double> x(n), y(n), mx(n), my(n);
@@ -654,6 +656,46 @@ asi_status asi_magnetization(asi_handle h, double* m_out) {
                        h->stream);
   HIPCHK(hipMemcpyAsync(m_out, h->dMpart + kMagPartials, 16, hipMemcpyDeviceToHost, h->stream), h);
   return sync_and_check(h);
+}
+
+asi_status asi_spin_correlation(asi_handle h, const double* xy, double bin_width,
+                                int32_t n_bins, int64_t* sum_out, int64_t* count_out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (!xy || !sum_out || !count_out) return fail(ASI_EINVAL, "NULL argument");
+  if (!(bin_width > 0.0) || !std::isfinite(bin_width))
+    return fail(ASI_EINVAL, "bin_width must be finite and > 0");
+  if (n_bins < 1 || n_bins > kCorrMaxBins) return fail(ASI_EINVAL, "n_bins out of range");
+  for (int64_t k = 0; k < 2 * h->n; ++k)
+    if (!std::isfinite(xy[k])) return fail(ASI_EINVAL, "non-finite position");
+  HIPCHK(hipStreamSynchronize(h->stream), h);
+  double* dxy = dalloc<double>(h, 2 * h->n);
+  uint64_t* dsc = dalloc<uint64_t>(h, 2 * (int64_t)n_bins);
+  if (!dxy || !dsc) {
+    if (dxy) h->mem.release(dxy);
+    if (dsc) h->mem.release(dsc);
+    return fail(ASI_ENOMEM, "device allocation failed (correlation)");
+  }
+  asi_status rs = ASI_OK;
+  hipError_t e = hipMemcpyAsync(dxy, xy, 16 * h->n, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(dsc, 0, 16 * (size_t)n_bins, h->stream);
+  if (e == hipSuccess) {
+    launch_correlation(h->dI, h->n, dxy, bin_width, n_bins, std::fabs(h->alpha), dsc,
+                       dsc + n_bins, h->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(sum_out, dsc, 8 * (size_t)n_bins, hipMemcpyDeviceToHost,
+                                          h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(count_out, dsc + n_bins, 8 * (size_t)n_bins,
+                                          hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    rs = fail(ASI_EDEVICE, std::string("correlation: ") + hipGetErrorString(e));
+  }
+  h->mem.release(dxy);
+  h->mem.release(dsc);
+  return rs;
 }
 
 asi_status asi_set_magnetization_log(asi_handle h, int32_t enable) {

@@ -671,6 +671,49 @@ def test_magnetisation_log_follows_the_flip_log():
         gpu_sim(w).magnetization_log()
 
 
+# ------------------------------------------------------------------ spin-spin correlation (Sec. IV.B)
+def test_spin_correlation_bit_exact():
+    """Per-bin correlation sums and pair counts (integers) equal the
+    oracle's for random states on a ragged kagome patch, a pinwheel at 7
+    lattice units and the 20 x 20 square before and after annealing; the
+    annealed state is more correlated at the nearest separation."""
+    xy, theta = W.kagome(16, 15)
+    n = len(theta)
+    cases = [W.Workload("kagome16x15", xy, theta, np.ones(n, np.int8), np.full(n, 0.2),
+                        np.zeros((2, 2)), alpha=0.002, neighbor_distance=3.0, b=1, c=1,
+                        beta=3, gamma=3)]
+    xy, theta = W.pinwheel_diamond(23)
+    n = len(theta)
+    cases.append(W.Workload("pinwheel23_d7", xy, theta, np.ones(n, np.int8), np.full(n, 0.2),
+                            np.zeros((2, 2)), alpha=0.0013, neighbor_distance=7.0, b=1, c=1,
+                            beta=3, gamma=3))
+    rng = np.random.default_rng(12)
+    for w in cases:
+        say("correlation", w.name, w.n)
+        sim = gpu_sim(w)
+        o = N.Oracle.from_workload(w)
+        for width, nb in ((0.25, 13), (0.5, 9)):
+            s = rng.choice([-1, 1], w.n).astype(np.int8)
+            sim.set_state(s, -1)
+            gs, gc = sim.spin_correlation(w.xy, width, nb)
+            es, ec = o.spin_correlation(width, nb, s)
+            assert np.array_equal(gc, ec) and np.array_equal(gs, es), (gs, es, gc, ec)
+            assert gc.sum() > 0
+    w = W.square_anneal(side=20, n_steps=100)
+    sim = gpu_sim(w)
+    o = N.Oracle.from_workload(w)
+    b_nn = int(np.floor(np.sqrt(0.5) / 0.25))
+    before = sim.spin_correlation(w.xy, 0.25, 41)
+    sim.run()
+    after = sim.spin_correlation(w.xy, 0.25, 41)
+    ref = o.spin_correlation(0.25, 41, sim.state()[0])
+    assert np.array_equal(after[0], ref[0]) and np.array_equal(after[1], ref[1])
+    assert np.array_equal(before[1], after[1])
+    assert after[0][b_nn] / after[1][b_nn] > before[0][b_nn] / before[1][b_nn]
+    with pytest.raises(asi.AsiError):
+        sim.spin_correlation(w.xy, 0.0, 4)
+
+
 # ------------------------------------------------------------------ edge cases
 def test_single_magnet_and_no_neighbours():
     say("single magnet")
