@@ -6,6 +6,7 @@ benchmark's CPU-baseline leg, never by the product path.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -171,6 +172,17 @@ class Oracle:
         for the current spins or the given ones."""
         s = (self.spins() if spins is None else np.asarray(spins)).astype(np.float64)
         return np.array([np.sum(s * np.cos(self.theta)), np.sum(s * np.sin(self.theta))])
+
+    def group_magnetization(self, ptr, idx, spins=None):
+        """[G, 2]: sum of s_i mhat_i over each CSR group (a vertex map when
+        the groups are the islands meeting at each vertex)."""
+        s = (self.spins() if spins is None else np.asarray(spins)).astype(np.float64)
+        out = np.zeros((len(ptr) - 1, 2))
+        for g in range(len(ptr) - 1):
+            for i in idx[ptr[g]:ptr[g + 1]]:
+                out[g, 0] += s[i] * math.cos(self.theta[i])
+                out[g, 1] += s[i] * math.sin(self.theta[i])
+        return out
 
     def spin_correlation(self, bin_width, n_bins, spins=None):
         """(sums, counts) per distance bin of the pair correlation (Sec.

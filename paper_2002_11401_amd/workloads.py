@@ -99,6 +99,31 @@ def ising(nx: int, ny: Optional[int] = None):
     return np.ascontiguousarray(xy), np.zeros(len(xy))
 
 
+def square_vertices(n_side: int):
+    """The islands meeting at each vertex (x, y) of square_closed(n_side),
+    vertices row-major, islands in index order: (ptr [V+1], idx, vxy [V,2])."""
+    n = int(n_side)
+    xy, theta = square_closed(n)
+    nh = n * (n + 1)
+    ptr, idx, vxy = [0], [], []
+    for y in range(n + 1):
+        for x in range(n + 1):
+            members = []
+            if x > 0:
+                members.append(y * n + (x - 1))          # horizontal to the left
+            if x < n:
+                members.append(y * n + x)                # horizontal to the right
+            if y > 0:
+                members.append(nh + (y - 1) * (n + 1) + x)   # vertical below
+            if y < n:
+                members.append(nh + y * (n + 1) + x)         # vertical above
+            idx.extend(sorted(members))
+            ptr.append(len(idx))
+            vxy.append((float(x), float(y)))
+    return (np.asarray(ptr, dtype=np.int64), np.asarray(idx, dtype=np.int32),
+            np.asarray(vxy, dtype=np.float64))
+
+
 def kagome(nu: int, nv: Optional[int] = None):
     """Kagome ASI on nu x nv honeycomb cells (3 islands per cell)."""
     nu = int(nu)

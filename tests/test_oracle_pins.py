@@ -654,3 +654,30 @@ def test_p15_correlation_of_square_ground_state_vertex_pairs():
     assert cnts[b_nn] == 4 * n * n and sums[b_nn] == cnts[b_nn]
     su, cu = o.spin_correlation(w, 11, np.ones(len(theta), np.int8))
     assert cu[b_nn] == cnts[b_nn] and su[b_nn] < cu[b_nn]
+
+
+# ---------------------------------------------------------------- P16: vertex maps
+def test_p16_vertex_magnetisation_type_one_and_uniform():
+    """Vertex maps (Sec. IV.B): in the type-I ground state every interior
+    vertex of the square lattice has zero net magnetisation (two in, two out,
+    the ins opposite); in the uniform state every interior vertex carries
+    (2, 2) (two horizontal +x, two vertical +y islands)."""
+    n = 6
+    xy, theta = W.square_closed(n)
+    ptr, idx, vxy = W.square_vertices(n)
+    o = N.Oracle(**_model(xy, theta, np.full(len(theta), 0.2), 0.01, 1.0))
+    horiz = theta == 0.0
+    vx = np.where(horiz, np.floor(xy[:, 0]), np.round(xy[:, 0]))
+    vy = np.where(horiz, np.round(xy[:, 1]), np.floor(xy[:, 1]))
+    even = (vx + vy) % 2 == 0
+    s = np.where(horiz, np.where(even, -1, 1), np.where(even, 1, -1)).astype(np.int8)
+    interior = (vxy[:, 0] > 0) & (vxy[:, 0] < n) & (vxy[:, 1] > 0) & (vxy[:, 1] < n)
+    m = o.group_magnetization(ptr, idx, s)
+    assert np.all(np.abs(m[interior]) < 1e-15)
+    assert np.all(np.hypot(m[~interior, 0], m[~interior, 1]) > 0.9)   # open boundary vertices
+    mu = o.group_magnetization(ptr, idx, np.ones(len(theta), np.int8))
+    np.testing.assert_allclose(mu[interior], 2.0, atol=1e-15)
+    # the vertex sums add up to twice the net magnetisation (each island
+    # belongs to two vertices)
+    np.testing.assert_allclose(mu.sum(0), 2 * o.magnetization(np.ones(len(theta), np.int8)),
+                               rtol=1e-14)

@@ -151,3 +151,15 @@ def test_local_field_and_schedule_generators():
     assert np.allclose(wv[4], W.travelling_wave(xy, 1, 0.1, 3.0, 4, 0.0)[0])  # period 4 steps
     s = W.exponential_anneal(11, 0.2, 0.002)
     assert s[0] == 0.2 and abs(s[-1] - 0.002) < 1e-15 and np.allclose(s[1:] / s[:-1], 0.01 ** 0.1)
+
+
+def test_square_vertices_groups():
+    n = 5
+    xy, theta = W.square_closed(n)
+    ptr, idx, vxy = W.square_vertices(n)
+    assert len(ptr) == (n + 1) ** 2 + 1 and ptr[-1] == len(idx) == 2 * len(theta)
+    for g in range(len(ptr) - 1):
+        members = idx[ptr[g]:ptr[g + 1]]
+        assert np.allclose(np.hypot(*(xy[members] - vxy[g]).T), 0.5)
+        inner = 0 < vxy[g, 0] < n and 0 < vxy[g, 1] < n
+        assert len(members) == (4 if inner else len(members)) and 2 <= len(members) <= 4
