@@ -139,6 +139,14 @@ asi_status asi_set_thermal_schedule(asi_handle h, int64_t n_steps, const double*
  * m_out: host double[2] (x, y). */
 asi_status asi_magnetization(asi_handle h, double* m_out);
 
+/* Net magnetisation of groups of magnets, e.g. the islands that meet at each
+ * vertex (the vertex maps of Sec. IV.B): group g is idx[ptr[g] .. ptr[g+1])
+ * (CSR, host arrays, ptr[0] = 0, non-decreasing, 0 <= idx < n), and out[2g],
+ * out[2g+1] (host) receive sum s_i mhat_i over it, added in that order.
+ * ASI_EINVAL for malformed groups (checked before any device work). */
+asi_status asi_group_magnetization(asi_handle h, int64_t n_groups, const int64_t* ptr,
+                                   const int32_t* idx, double* out);
+
 /* Spin-spin correlation by separation (Sec. IV.B), over the neighbour pairs
  * of the instance (Sec. II.C), each pair once.  A pair correlates +1 when its
  * dipolar energy -s_i s_j A_ij is minimal (s_i s_j A_ij > 0, A_ij the

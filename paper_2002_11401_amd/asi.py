@@ -94,6 +94,7 @@ SIGNATURES = {
     "asi_set_thermal_schedule": [P, C.c_int64, P],
     "asi_magnetization": [P, P],
     "asi_spin_correlation": [P, P, C.c_double, C.c_int32, P, P],
+    "asi_group_magnetization": [P, C.c_int64, P, P, P],
     "asi_set_magnetization_log": [P, C.c_int32],
     "asi_get_magnetization_log": [P, P],
     "asi_relax": [P, I64P],
@@ -327,6 +328,19 @@ class Sim:
         _check(library().asi_spin_correlation(self.handle, _ptr(xy), float(bin_width),
                                               int(n_bins), _ptr(s), _ptr(c)))
         return s, c
+
+    def group_magnetization(self, ptr, idx) -> np.ndarray:
+        """[G, 2]: net magnetisation of each CSR group of magnets (e.g. the
+        islands of each vertex)."""
+        ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        if len(ptr) < 2 or ptr[-1] > len(idx):
+            raise ValueError("ptr must have G+1 entries ending at most at len(idx)")
+        out = np.zeros((len(ptr) - 1, 2))
+        _check(library().asi_group_magnetization(self.handle, len(ptr) - 1, _ptr(ptr),
+                                                 _ptr(idx if len(idx) else np.zeros(1, np.int32)),
+                                                 _ptr(out)))
+        return out
 
     def set_magnetization_log(self, on: bool = True):
         _check(library().asi_set_magnetization_log(self.handle, 1 if on else 0))

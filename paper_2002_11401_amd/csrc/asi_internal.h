@@ -115,6 +115,11 @@ void launch_draw_hk(double* hk, int64_t n, double mean, double k, uint64_t seed,
 constexpr int kMagPartials = 2 * 256;
 void launch_magnetization(const int8_t* s, const double* mx, const double* my, int64_t n,
                           double* part, double* out, hipStream_t st);
+// Net magnetisation of each CSR group of magnets (ptr [ngroups+1], idx on
+// the device, indices validated by the caller) into out[ngroups][2].
+void launch_group_magnetization(const int8_t* s, const double* mx, const double* my,
+                                const int64_t* ptr, const int32_t* idx, int64_t ngroups,
+                                double* out, hipStream_t st);
 // Spin-spin correlation sums and pair counts per distance bin (two's
 // complement sums) over the instance's neighbour pairs; xy is on the device.
 constexpr int kCorrMaxBins = 4096;

@@ -1989,6 +1989,26 @@ k_mag_final(const double* __restrict__ part, double* __restrict__ out) {
 
 static_assert(2 * kMagBlocks == kMagPartials, "block sums buffer");
 
+// Net magnetisation of groups of magnets, e.g. the islands meeting at each
+// vertex (the vertex maps of Sec. IV.B): group g sums s_i mhat_i over
+// idx[ptr[g] .. ptr[g+1]) in that order, one thread per group.
+__global__ void __launch_bounds__(256)
+k_group_mag(const int8_t* __restrict__ s, const double* __restrict__ mx,
+            const double* __restrict__ my, const int64_t* __restrict__ ptr,
+            const int32_t* __restrict__ idx, int64_t ngroups, double* __restrict__ out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ngroups) return;
+  double ax = 0.0, ay = 0.0;
+  for (int64_t e = ptr[g]; e < ptr[g + 1]; ++e) {
+    const int32_t i = idx[e];
+    const bool up = s[i] > 0;
+    ax = ax + (up ? mx[i] : -mx[i]);
+    ay = ay + (up ? my[i] : -my[i]);
+  }
+  out[2 * g] = ax;
+  out[2 * g + 1] = ay;
+}
+
 // Spin-spin correlation by separation (Sec. IV.B): a pair (i, j) of
 // neighbours correlates +1 when its dipolar energy -s_i s_j A_ij is at its
 // minimum (s_i s_j A_ij > 0), -1 at its maximum, and 0 when the coupling
@@ -2048,6 +2068,14 @@ void launch_correlation(const InstDev* inst, int64_t n, const double* xy, double
                      inst, xy, w, nbins, abs_alpha,
                      reinterpret_cast<unsigned long long*>(sum),
                      reinterpret_cast<unsigned long long*>(cnt));
+}
+
+void launch_group_magnetization(const int8_t* s, const double* mx, const double* my,
+                                const int64_t* ptr, const int32_t* idx, int64_t ngroups,
+                                double* out, hipStream_t st) {
+  const int64_t blocks = (ngroups + 255) / 256;
+  hipLaunchKernelGGL(k_group_mag, dim3((unsigned)blocks), dim3(256), 0, st, s, mx, my, ptr, idx,
+                     ngroups, out);
 }
 
 void launch_magnetization(const int8_t* s, const double* mx, const double* my, int64_t n,

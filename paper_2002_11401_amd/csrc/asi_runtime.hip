@@ -698,6 +698,48 @@ asi_status asi_spin_correlation(asi_handle h, const double* xy, double bin_width
   return rs;
 }
 
+asi_status asi_group_magnetization(asi_handle h, int64_t n_groups, const int64_t* ptr,
+                                   const int32_t* idx, double* out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (n_groups < 1 || n_groups >= ((int64_t)1 << 31) || !ptr || !idx || !out)
+    return fail(ASI_EINVAL, "bad groups");
+  if (ptr[0] != 0) return fail(ASI_EINVAL, "ptr[0] must be 0");
+  for (int64_t g = 0; g < n_groups; ++g)
+    if (ptr[g + 1] < ptr[g]) return fail(ASI_EINVAL, "ptr must not decrease");
+  const int64_t ne = ptr[n_groups];
+  for (int64_t e = 0; e < ne; ++e)
+    if (idx[e] < 0 || idx[e] >= h->n) return fail(ASI_EINVAL, "magnet index out of range");
+  HIPCHK(hipStreamSynchronize(h->stream), h);
+  int64_t* dptr = dalloc<int64_t>(h, n_groups + 1);
+  int32_t* didx = dalloc<int32_t>(h, std::max<int64_t>(1, ne));
+  double* dout = dalloc<double>(h, 2 * n_groups);
+  asi_status rs = ASI_OK;
+  hipError_t e = (dptr && didx && dout) ? hipSuccess : hipErrorOutOfMemory;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dptr, ptr, 8 * (n_groups + 1), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess && ne > 0)
+    e = hipMemcpyAsync(didx, idx, 4 * ne, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) {
+    launch_group_magnetization(h->hI.s, h->hI.mx, h->hI.my, dptr, didx, n_groups, dout,
+                               h->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, dout, 16 * n_groups, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipErrorOutOfMemory && !(dptr && didx && dout)) {
+    rs = fail(ASI_ENOMEM, "device allocation failed (groups)");
+  } else if (e != hipSuccess) {
+    h->poisoned = true;
+    rs = fail(ASI_EDEVICE, std::string("group magnetisation: ") + hipGetErrorString(e));
+  }
+  h->mem.release(dptr);
+  h->mem.release(didx);
+  h->mem.release(dout);
+  return rs;
+}
+
 asi_status asi_set_magnetization_log(asi_handle h, int32_t enable) {
   asi_status st = check_handle(h);
   if (st != ASI_OK) return st;

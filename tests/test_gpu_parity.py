@@ -671,6 +671,34 @@ def test_magnetisation_log_follows_the_flip_log():
         gpu_sim(w).magnetization_log()
 
 
+def test_vertex_maps():
+    """Net magnetisation per vertex of a 30 x 30 square array for random and
+    annealed states, within rounding of the oracle's sums; malformed groups
+    are rejected before any device work."""
+    w = W.square_anneal(side=30, n_steps=60)
+    ptr, idx, vxy = W.square_vertices(30)
+    say("vertex maps", w.n, len(ptr) - 1)
+    sim = gpu_sim(w)
+    o = N.Oracle.from_workload(w)
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        s = rng.choice([-1, 1], w.n).astype(np.int8)
+        sim.set_state(s, -1)
+        m = sim.group_magnetization(ptr, idx)
+        assert np.all(np.abs(m - o.group_magnetization(ptr, idx, s)) <= 4 * MAG_TOL)
+    sim.set_state(w.spin0, -1)
+    sim.run()
+    m = sim.group_magnetization(ptr, idx)
+    assert np.all(np.abs(m - o.group_magnetization(ptr, idx, sim.state()[0])) <= 4 * MAG_TOL)
+    assert np.abs(m.sum(0) - 2 * sim.magnetization()).max() < 1e-9
+    bad = idx.copy()
+    bad[3] = w.n
+    with pytest.raises(asi.AsiError):
+        sim.group_magnetization(ptr, bad)
+    with pytest.raises(asi.AsiError):
+        sim.group_magnetization(ptr[::-1].copy(), idx)
+
+
 # ------------------------------------------------------------------ spin-spin correlation (Sec. IV.B)
 def test_spin_correlation_bit_exact():
     """Per-bin correlation sums and pair counts (integers) equal the
