@@ -295,6 +295,13 @@ asi_status asi_server_create(const asi_device* dev, size_t hbm_budget_bytes,
  * budget. */
 asi_status asi_server_submit(asi_server_t s, const asi_params* p, int64_t n_steps,
                              const double* h_xy, int64_t* job_id_out);
+/* The same with the per-magnet external field of asi_set_local_field
+ * (loc_slabs 0, 1 or n_steps; h_loc host [loc_slabs][n][2]) and the thermal
+ * schedule of asi_set_thermal_schedule (sigma host [n_steps], or NULL for
+ * thermal_std), copied and applied at admission; the footprint counts them. */
+asi_status asi_server_submit_fields(asi_server_t s, const asi_params* p, int64_t n_steps,
+                                    const double* h_xy, int64_t loc_slabs, const double* h_loc,
+                                    const double* sigma, int64_t* job_id_out);
 /* Advance the server by one burst: run every resident job for about
  * budget_ms of device time (each job's workgroup advancing through its own
  * protocol; a relax still running at the deadline pauses mid-step and

@@ -112,6 +112,7 @@ SIGNATURES = {
     "asi_batch_run": [P, C.c_int32, C.c_int32, P],
     "asi_server_create": [C.POINTER(AsiDevice), C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)],
     "asi_server_submit": [P, C.POINTER(AsiParams), C.c_int64, P, I64P],
+    "asi_server_submit_fields": [P, C.POINTER(AsiParams), C.c_int64, P, C.c_int64, P, P, I64P],
     "asi_server_step": [P, C.c_double, C.POINTER(C.c_int32)],
     "asi_server_poll": [P, C.c_int64, C.POINTER(C.c_int32)],
     "asi_server_take": [P, C.c_int64, P, I64P, C.POINTER(C.c_uint64),
@@ -466,7 +467,24 @@ class Server:
         p, keep = _params(w.xy, w.theta, w.hk, w.spin0, **w.params(), **kw)
         H = np.ascontiguousarray(w.H, dtype=np.float64).reshape(-1, 2)
         jid = C.c_int64(0)
-        _check(library().asi_server_submit(self._h, C.byref(p), len(H), _ptr(H), C.byref(jid)))
+        loc = getattr(w, "h_loc", None)
+        sig = getattr(w, "sigma_t", None)
+        if loc is None and sig is None:
+            _check(library().asi_server_submit(self._h, C.byref(p), len(H), _ptr(H),
+                                               C.byref(jid)))
+        else:
+            if loc is not None:
+                loc = np.ascontiguousarray(loc, dtype=np.float64)
+                loc = loc[None] if loc.ndim == 2 else loc
+                if loc.ndim != 3 or loc.shape[1:] != (len(keep[1]), 2):
+                    raise ValueError("h_loc must be (n, 2) or (K, n, 2)")
+            if sig is not None:
+                sig = np.ascontiguousarray(sig, dtype=np.float64).reshape(-1)
+                if len(sig) != len(H):
+                    raise ValueError("sigma_t needs one value per protocol step")
+            _check(library().asi_server_submit_fields(
+                self._h, C.byref(p), len(H), _ptr(H), 0 if loc is None else loc.shape[0],
+                _ptr(loc), _ptr(sig), C.byref(jid)))
         self._n[jid.value] = len(keep[1])
         return jid.value
 

@@ -1270,6 +1270,8 @@ struct Job {
   int64_t id = 0;
   asi_params p{};
   std::vector<double> xy, theta, hk, H;
+  std::vector<double> loc, sig;   // local field [loc_k][n][2], thermal schedule [K] (optional)
+  int64_t loc_k = 0;
   std::vector<int8_t> spin0;
   int64_t K = 0;
   size_t foot = 0;
@@ -1419,6 +1421,8 @@ asi_status server_admit(asi_server* S) {
     asi_handle h = nullptr;
     asi_status st = asi_create(&p, &S->cdev, &h);
     if (st == ASI_OK) st = asi_set_field_protocol(h, J.K, J.H.data());
+    if (st == ASI_OK && J.loc_k > 0) st = asi_set_local_field(h, J.loc_k, J.loc.data());
+    if (st == ASI_OK && !J.sig.empty()) st = asi_set_thermal_schedule(h, J.K, J.sig.data());
     if (st != ASI_OK) {
       if (h) asi_destroy(h);
       J.state = 3;
@@ -1504,11 +1508,28 @@ asi_status asi_server_create(const asi_device* dev, size_t hbm_budget_bytes, int
 
 asi_status asi_server_submit(asi_server_t S, const asi_params* p, int64_t n_steps,
                              const double* h_xy, int64_t* job_id_out) {
+  return asi_server_submit_fields(S, p, n_steps, h_xy, 0, nullptr, nullptr, job_id_out);
+}
+
+asi_status asi_server_submit_fields(asi_server_t S, const asi_params* p, int64_t n_steps,
+                                    const double* h_xy, int64_t loc_slabs, const double* h_loc,
+                                    const double* sigma, int64_t* job_id_out) {
   if (!S || !job_id_out) return fail(ASI_EINVAL, "null argument");
   asi_status st = validate(p);
   if (st != ASI_OK) return st;
   if (n_steps < 1 || !h_xy) return fail(ASI_EINVAL, "a job needs a protocol of >= 1 step");
+  if (loc_slabs < 0 || (loc_slabs > 1 && loc_slabs != n_steps) || (loc_slabs > 0 && !h_loc))
+    return fail(ASI_EINVAL, "bad local field: loc_slabs must be 0, 1 or n_steps");
+  for (int64_t k = 0; k < 2 * loc_slabs * p->n; ++k)
+    if (!std::isfinite(h_loc[k])) return fail(ASI_EINVAL, "non-finite local field value");
+  if (sigma)
+    for (int64_t k = 0; k < n_steps; ++k)
+      if (!(sigma[k] >= 0.0) || !std::isfinite(sigma[k]))
+        return fail(ASI_EINVAL, "thermal schedule values must be finite and >= 0");
   auto J = std::make_unique<Job>();
+  if (loc_slabs > 0) J->loc.assign(h_loc, h_loc + 2 * loc_slabs * p->n);
+  J->loc_k = loc_slabs;
+  if (sigma) J->sig.assign(sigma, sigma + n_steps);
   J->p = *p;
   J->xy.assign(p->xy, p->xy + 2 * p->n);
   J->theta.assign(p->theta, p->theta + p->n);
@@ -1517,7 +1538,8 @@ asi_status asi_server_submit(asi_server_t S, const asi_params* p, int64_t n_step
   J->H.assign(h_xy, h_xy + 2 * n_steps);
   J->K = n_steps;
   const int64_t log_cap = p->flip_log_capacity > 0 ? p->flip_log_capacity : 4 * p->n + 65536;
-  J->foot = footprint_estimate(p->n, degree_bound(p), n_steps, log_cap);
+  J->foot = footprint_estimate(p->n, degree_bound(p), n_steps, log_cap) +
+            (size_t)(16 * loc_slabs * p->n) + (sigma ? (size_t)(8 * n_steps) : 0);
   if (J->foot > S->budget) return fail(ASI_ENOMEM, "job footprint exceeds the server budget");
   J->id = S->next_id++;
   *job_id_out = J->id;

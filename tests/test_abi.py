@@ -63,6 +63,8 @@ def test_invalid_arguments_fail_before_touching_the_device():
     assert lib.asi_set_magnetization_log(None, 1) == asi.ASI_EINVAL
     assert lib.asi_get_magnetization_log(None, None) == asi.ASI_EINVAL
     assert lib.asi_server_step(None, 1.0, None) == asi.ASI_EINVAL
+    assert lib.asi_server_submit_fields(None, None, 1, None, 0, None, None,
+                                        None) == asi.ASI_EINVAL
     assert lib.asi_server_destroy(None) == asi.ASI_OK
 
 

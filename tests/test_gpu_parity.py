@@ -262,6 +262,45 @@ def test_served_equals_plain_bitwise(budget_ms, big, slots, count, monkeypatch):
     srv.close()
 
 
+@pytest.mark.parametrize("budget_ms", [20.0, 0.002])
+def test_served_local_fields_and_schedules_bitwise(budget_ms):
+    """Served jobs carrying static or per-step local fields and thermal
+    schedules (paused mid-step at the short budget) equal their plain runs
+    bit for bit, and one of them the oracle."""
+    jobs = W.served_stream(count=8, seed=15, n_range=(200, 3000), steps_range=(20, 50))
+    ws = []
+    for k, job in enumerate(jobs):
+        w = job.workload()
+        if k % 3 == 0:
+            w.h_loc = W.spatial_gradient(w.xy, 0.002, 30.0 * k, 10.0 * k)
+        elif k % 3 == 1:
+            w.h_loc = W.travelling_wave(w.xy, w.n_steps, 0.04, 6.0, 10, 20.0 * k)
+        if k % 2 == 0:
+            w.sigma_t = W.exponential_anneal(w.n_steps, 0.02, 0.001)
+        ws.append(w)
+    say("served local fields", budget_ms, [w.n for w in ws])
+    srv = asi.Server(hbm_budget_bytes=2 << 30, max_slots=4)
+    ids = [srv.submit(w) for w in ws]
+    for _ in range(200000):
+        srv.step(budget_ms=budget_ms)
+        if srv.stats()["retired"] == len(ws):
+            break
+    st = srv.stats()
+    assert st["admitted"] == st["retired"] == len(ws)
+    hashes = []
+    for w, jid in zip(ws, ids):
+        res = srv.take(jid)
+        s = gpu_sim(w)
+        s.run()
+        lg = s.flip_log()
+        assert res["flips"] == lg["count"] and res["hash"] == lg["hash"]
+        assert np.array_equal(res["spins"], s.state()[0])
+        hashes.append(res["hash"])
+    o, r = oracle_run(ws[0], log_cap=10 ** 6)
+    assert asi.flip_hash(r["step"], r["idx"]) == hashes[0]
+    srv.close()
+
+
 def test_large_pool_with_tied_keys():
     """Uniform h_k, no coupling, field along the diagonal: every magnet of a
     9,940-magnet square lattice starts the first step flippable, and each of
