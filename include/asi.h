@@ -124,6 +124,15 @@ asi_status asi_set_field_protocol(asi_handle h, int64_t n_steps, const double* h
  * 1) is set, asi_set_field_protocol accepts only the same length. */
 asi_status asi_set_local_field(asi_handle h, int64_t n_slabs, const double* h_loc);
 
+/* Travelling-wave local field evaluated in the field pass (Sec. II.D), no
+ * per-step storage: magnet i at step t gets
+ *   amp * sin(2 pi (kx x_i + ky y_i) + phase0 - 2 pi t / period_steps) * (cos angle, sin angle)
+ * added to H[t] and to any asi_set_local_field field.  xy: host [2n], the
+ * instance's positions (8 bytes per magnet are kept on the device).  All
+ * values finite, period_steps != 0; amp == 0 removes the wave. */
+asi_status asi_set_local_wave(asi_handle h, const double* xy, double amp, double kx, double ky,
+                              double period_steps, double phase0, double angle);
+
 /* Thermal schedule (Sec. II.E; the annealing protocols of Sec. IV.B): step t
  * draws its thermal field with standard deviation sigma[t] instead of
  * thermal_std (same normals: Philox counter (i, t, 0, 0)), so a constant
@@ -220,7 +229,8 @@ typedef struct {
   int64_t device_bytes;     /* device memory held by the handle                  */
   double field_pass_bytes;  /* algorithmic bytes of one full-field pass:
                                20 per neighbour pair + 53 per magnet, + 16
-                               per magnet with a local field set              */
+                               per magnet with a local field set, + 8 with a
+                               local wave                                     */
   int64_t flip_log_capacity;/* flip-log entries kept (asi_params)               */
 } asi_info;
 asi_status asi_get_info(asi_handle h, asi_info* out);

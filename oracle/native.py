@@ -147,18 +147,43 @@ class Oracle:
 
     def set_local_field(self, h_loc):
         """Local external field (Sec. II.D): (n, 2) for every step, (K, n, 2)
-        one slab per step, None for none."""
-        if h_loc is None:
-            self._loc = None
-            self._loc_k = 0
+        one slab per step, None for none.  Adds to any wave set below."""
+        self._user_loc = None if h_loc is None else np.ascontiguousarray(h_loc, dtype=np.float64)
+        if self._user_loc is not None and self._user_loc.ndim == 2:
+            self._user_loc = self._user_loc[None]
+        if self._user_loc is not None:
+            assert self._user_loc.ndim == 3 and self._user_loc.shape[1:] == (self.n, 2)
+        self._push_local()
+
+    def set_local_wave(self, amp, kx, ky, period_steps, phase0, angle_rad, n_steps):
+        """Travelling-wave local field of each step t < n_steps:
+        amp sin(2 pi (kx x_i + ky y_i) + phase0 - 2 pi t / period_steps)
+        along (cos, sin)(angle); amp = 0 removes it."""
+        if amp == 0.0:
+            self._wave = None
+        else:
+            t = np.arange(int(n_steps), dtype=np.float64)[:, None]
+            arg = 2.0 * np.pi * (kx * self.xy[:, 0] + ky * self.xy[:, 1])[None, :] + phase0 \
+                - 2.0 * np.pi * t / period_steps
+            a = amp * np.sin(arg)
+            self._wave = np.stack([a * math.cos(angle_rad), a * math.sin(angle_rad)], axis=2)
+        self._push_local()
+
+    def _push_local(self):
+        loc = getattr(self, "_user_loc", None)
+        wave = getattr(self, "_wave", None)
+        if loc is None and wave is None:
+            self._loc, self._loc_k = None, 0
             lib().orc_set_local_field(self._h, 0, None)
             return
-        a = np.ascontiguousarray(h_loc, dtype=np.float64)
-        if a.ndim == 2:
-            a = a[None]
-        assert a.ndim == 3 and a.shape[1:] == (self.n, 2), a.shape
-        self._loc = a
-        self._loc_k = a.shape[0]
+        if wave is None:
+            a = loc
+        elif loc is None:
+            a = wave
+        else:
+            a = wave + loc      # a static field broadcasts over the wave's steps
+        a = np.ascontiguousarray(a)
+        self._loc, self._loc_k = a, a.shape[0]
         lib().orc_set_local_field(self._h, a.shape[0], _vp(a))
 
     def set_thermal_schedule(self, sigma):

@@ -92,6 +92,7 @@ SIGNATURES = {
     "asi_set_field_protocol": [P, C.c_int64, P],
     "asi_set_local_field": [P, C.c_int64, P],
     "asi_set_thermal_schedule": [P, C.c_int64, P],
+    "asi_set_local_wave": [P, P] + [C.c_double] * 6,
     "asi_magnetization": [P, P],
     "asi_spin_correlation": [P, P, C.c_double, C.c_int32, P, P],
     "asi_group_magnetization": [P, C.c_int64, P, P, P],
@@ -301,6 +302,17 @@ class Sim:
         if a.ndim != 3 or a.shape[1] != self.n or a.shape[2] != 2:
             raise ValueError("h_loc must be (n, 2) or (K, n, 2)")
         _check(library().asi_set_local_field(self.handle, a.shape[0], _ptr(a)))
+
+    def set_local_wave(self, xy, amp, kx, ky, period_steps, phase0=0.0, angle_deg=0.0):
+        """Travelling-wave local field evaluated on the device: amp * sin(2 pi
+        (kx x + ky y) + phase0 - 2 pi t / period_steps) along angle_deg;
+        amp = 0 removes it."""
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        if len(xy) != self.n:
+            raise ValueError("xy must hold the n positions")
+        _check(library().asi_set_local_wave(self.handle, _ptr(xy), float(amp), float(kx),
+                                            float(ky), float(period_steps), float(phase0),
+                                            np.deg2rad(float(angle_deg))))
 
     def set_thermal_schedule(self, sigma):
         """Thermal std of every step (length K), or None for thermal_std."""

@@ -59,6 +59,10 @@ struct InstDev {
   int64_t K;
   const double2* hloc;    // [hloc_k][n] per-magnet external field (x, y), or null
   int64_t hloc_k;         // 1: the same field at every step; else one per step (== K)
+  // travelling-wave local field evaluated in the pass: wave_amp * sin(wave_ph[i]
+  // - wave_w * t) along (wave_ex, wave_ey); wave_ph null when none
+  const double* wave_ph;  // [n] 2 pi (k . r_i) + phase0
+  double wave_amp, wave_w, wave_ex, wave_ey;
   int32_t field_mode;     // FieldMode
   int32_t pad0;
   // mutable state

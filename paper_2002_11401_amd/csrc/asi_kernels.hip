@@ -382,6 +382,13 @@ __device__ __forceinline__ double field_finish(const InstDev* __restrict__ I, in
       hp = hp + (l.x * mxi + l.y * myi);
       hq = hq + (l.y * mxi - l.x * myi);
     }
+    if (I->wave_ph) {
+      // a travelling wave (Sec. II.D), evaluated here instead of stored per step
+      const double a = I->wave_amp * sin(I->wave_ph[i] - I->wave_w * (double)t);
+      const double lx = a * I->wave_ex, ly = a * I->wave_ey;
+      hp = hp + (lx * mxi + ly * myi);
+      hq = hq + (ly * mxi - lx * myi);
+    }
     const double sg = I->sigma_t ? I->sigma_t[t] : I->sigma;
     if (sg > 0.0) {
       double z0, z1;

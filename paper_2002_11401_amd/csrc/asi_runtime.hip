@@ -106,6 +106,7 @@ struct asi_sim {
   double* dH = nullptr;
   double* dHloc = nullptr;
   double* dSig = nullptr;
+  double* dWave = nullptr;
   double alpha = 0.0;
   double* dMpart = nullptr;   // [kMagPartials + 2] block sums, then the last result
   double* dMlog = nullptr;    // [K][2] magnetisation after each step's relax
@@ -624,6 +625,44 @@ asi_status asi_set_local_field(asi_handle h, int64_t n_slabs, const double* h_lo
   return sync_and_check(h);
 }
 
+asi_status asi_set_local_wave(asi_handle h, const double* xy, double amp, double kx, double ky,
+                              double period_steps, double phase0, double angle) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (!std::isfinite(amp) || !std::isfinite(kx) || !std::isfinite(ky) ||
+      !std::isfinite(period_steps) || period_steps == 0.0 || !std::isfinite(phase0) ||
+      !std::isfinite(angle))
+    return fail(ASI_EINVAL, "wave parameters must be finite, period_steps != 0");
+  if (amp != 0.0 && !xy) return fail(ASI_EINVAL, "xy is NULL");
+  std::vector<double> ph;
+  if (amp != 0.0) {
+    ph.resize(h->n);
+    const double two_pi = 6.283185307179586;
+    for (int64_t i = 0; i < h->n; ++i) {
+      if (!std::isfinite(xy[2 * i]) || !std::isfinite(xy[2 * i + 1]))
+        return fail(ASI_EINVAL, "non-finite position");
+      ph[i] = two_pi * (kx * xy[2 * i] + ky * xy[2 * i + 1]) + phase0;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(h->stream), h);
+  if (h->dWave) h->mem.release(h->dWave);
+  h->dWave = nullptr;
+  if (amp != 0.0) {
+    h->dWave = dalloc<double>(h, h->n);
+    if (!h->dWave) return fail(ASI_ENOMEM, "device allocation failed (wave)");
+    HIPCHK(hipMemcpyAsync(h->dWave, ph.data(), 8 * h->n, hipMemcpyHostToDevice, h->stream), h);
+    HIPCHK(hipStreamSynchronize(h->stream), h);
+  }
+  h->hI.wave_ph = h->dWave;
+  h->hI.wave_amp = amp;
+  h->hI.wave_w = 6.283185307179586 / period_steps;
+  h->hI.wave_ex = std::cos(angle);
+  h->hI.wave_ey = std::sin(angle);
+  st = upload_desc(h);
+  if (st != ASI_OK) return st;
+  return sync_and_check(h);
+}
+
 asi_status asi_set_thermal_schedule(asi_handle h, int64_t n_steps, const double* sigma) {
   asi_status st = check_handle(h);
   if (st != ASI_OK) return st;
@@ -1045,7 +1084,8 @@ asi_status asi_get_info(asi_handle h, asi_info* out) {
   out->relax_waves = h->relax_waves;
   out->device_bytes = (int64_t)h->mem.total;
   out->field_pass_bytes = 20.0 * (double)h->E + 53.0 * (double)h->n +
-                          (h->hI.hloc ? 16.0 * (double)h->n : 0.0);
+                          (h->hI.hloc ? 16.0 * (double)h->n : 0.0) +
+                          (h->hI.wave_ph ? 8.0 * (double)h->n : 0.0);
   out->flip_log_capacity = h->hI.log_cap;
   return ASI_OK;
 }

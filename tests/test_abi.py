@@ -57,6 +57,7 @@ def test_invalid_arguments_fail_before_touching_the_device():
     assert lib.asi_set_tuning(None, None) == asi.ASI_EINVAL
     assert lib.asi_set_local_field(None, 1, None) == asi.ASI_EINVAL
     assert lib.asi_set_thermal_schedule(None, 1, None) == asi.ASI_EINVAL
+    assert lib.asi_set_local_wave(None, None, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0) == asi.ASI_EINVAL
     assert lib.asi_magnetization(None, None) == asi.ASI_EINVAL
     assert lib.asi_group_magnetization(None, 1, None, None, None) == asi.ASI_EINVAL
     assert lib.asi_spin_correlation(None, None, 1.0, 4, None, None) == asi.ASI_EINVAL

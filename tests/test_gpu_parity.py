@@ -456,6 +456,48 @@ def test_travelling_wave_series_bit_exact(mode):
         assert_fields_close(o, sim, w.H[t], t)
 
 
+@pytest.mark.parametrize("mode", ["carry", "full"])
+def test_local_wave_evaluated_on_device(mode):
+    """A travelling wave evaluated in the field pass (no per-step slabs),
+    alone and on top of a static spatial field, against the oracle; and
+    batched with plain instances, bitwise equal to plain runs."""
+    w = _gradient_kagome()
+    K = w.n_steps
+    wave = dict(amp=0.03, kx=0.11, ky=-0.05, period_steps=17.0, phase0=0.4, angle_deg=250.0)
+    for static in (False, True):
+        x = w if static else dataclasses.replace(w, h_loc=None)
+        say("local wave", x.n, mode, static)
+        sim = gpu_sim(x, field_mode=mode)
+        sim.set_local_wave(x.xy, **wave)
+        sim.run()
+        o = N.Oracle.from_workload(x)
+        o.set_local_wave(wave["amp"], wave["kx"], wave["ky"], wave["period_steps"],
+                         wave["phase0"], np.deg2rad(wave["angle_deg"]), K)
+        o.set_spins(x.spin0)
+        r = o.run(x.H)
+        assert_same_flips(sim.flip_log(), r, sim.state()[0], o.spins())
+        assert_fields_close(o, sim, x.H[-1], K - 1)
+    plain = gpu_sim(w, field_mode=mode)
+    plain.set_local_wave(w.xy, **wave)
+    plain.run()
+    ref = plain.flip_log(cap=0)
+    refs = []
+    for v in W.batched_sweep(count=3, seed=21, n_steps=30):
+        q = gpu_sim(v)
+        q.run()
+        refs.append(q.flip_log(cap=0))
+    batch = gpu_sim(w, field_mode=mode)
+    batch.set_local_wave(w.xy, **wave)
+    others2 = [gpu_sim(v) for v in W.batched_sweep(count=3, seed=21, n_steps=30)]
+    asi.batch_run([batch] + others2, mode="fused")
+    assert batch.flip_log(cap=0)["hash"] == ref["hash"]
+    for q, rf in zip(others2, refs):
+        assert q.flip_log(cap=0)["hash"] == rf["hash"]
+    batch.set_local_wave(w.xy, 0.0, 0.0, 0.0, 1.0)
+    with pytest.raises(asi.AsiError):
+        batch.set_local_wave(w.xy, 0.01, 0.1, 0.0, 0.0)
+
+
 def test_local_field_high_degree_and_updates():
     """The one-workgroup-per-slice pass (128+ neighbours) adds the local
     field like the per-lane pass; replacing and removing the field take

@@ -681,3 +681,20 @@ def test_p16_vertex_magnetisation_type_one_and_uniform():
     # belongs to two vertices)
     np.testing.assert_allclose(mu.sum(0), 2 * o.magnetization(np.ones(len(theta), np.int8)),
                                rtol=1e-14)
+
+
+def test_p11_wave_encoder_matches_the_wave_series():
+    """The oracle's travelling-wave encoder, sin(2 pi (k . r) + phase0 - 2 pi
+    t / T), equals the input generator's wave sin(2 pi (x / lambda - t / T))
+    for k = (1 / lambda, 0), phase0 = 0, and adds to a static local field."""
+    xy, theta = W.kagome(5, 4)
+    n, K = len(theta), 9
+    o = N.Oracle(**_model(xy, theta, np.full(n, 0.2), 0.0, 1.0))
+    o.set_local_wave(0.07, 1 / 6.0, 0.0, 4.0, 0.0, math.radians(35.0), K)
+    ref = W.travelling_wave(xy, K, 0.07, 6.0, 4, 35.0)
+    np.testing.assert_allclose(o._loc, ref, rtol=0, atol=1e-15)
+    st = W.random_local(n, 1, 0.01, 3)
+    o.set_local_field(st)
+    np.testing.assert_allclose(o._loc, ref + st[None], rtol=0, atol=1e-15)
+    o.set_local_wave(0.0, 0, 0, 1, 0, 0, K)
+    assert o._loc_k == 1 and np.array_equal(o._loc[0], st)
