@@ -100,6 +100,10 @@ def bench_plain(args, asi, workloads, torch):
     K = w.n_steps if args.steps is None else min(args.steps, w.n_steps)
     # every step re-gathers every row: the measured full-field pass
     sim = asi.Sim.from_workload(w, field_mode="full")
+    if args.local_field == "wave":
+        # a travelling wave evaluated in the pass (Sec. II.D): 0.02 along
+        # 200 deg, wavelength 40 lattice units along x, period 500 steps
+        sim.set_local_wave(w.xy, 0.02, 1.0 / 40.0, 0.0, 500.0, 0.0, 200.0)
     info = sim.info()
     E, N = info["n_edges"], info["n"]
     # warmup: the first steps, then back to the start state
@@ -155,7 +159,7 @@ def bench_plain(args, asi, workloads, torch):
                           "workload": "square ASI, 8-spin neighbourhood, saturated size"},
     }
     sim.close()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.local_field != "wave":
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     return out
 
@@ -312,8 +316,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--mode", choices=["plain", "batched", "served"], default="plain")
     ap.add_argument("--workload", default="kagome577_rotating")
-    ap.add_argument("--local-field", default="none", choices=["none", "gradient"],
-                    help="plain: add a static per-magnet spatial field")
+    ap.add_argument("--local-field", default="none", choices=["none", "gradient", "wave"],
+                    help="plain: add a static spatial field, or a travelling wave "
+                         "evaluated on the device (no CPU baseline for the wave)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--count", type=int, default=256, help="batched: instances")

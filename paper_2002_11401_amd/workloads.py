@@ -179,6 +179,22 @@ def triangle_ramp(half_steps: int, amp: float, angle_deg: float):
     return _along(np.concatenate([down, up]), angle_deg)
 
 
+def sinusoidal(n_steps: int, amp: float, steps_per_period: float, angle_deg: float,
+               phase_deg: float = 0.0):
+    """Field amp * sin(2 pi t / steps_per_period + phase) along a fixed angle."""
+    t = np.arange(int(n_steps), dtype=np.float64)
+    return _along(amp * np.sin(2.0 * np.pi * t / float(steps_per_period) + np.deg2rad(phase_deg)),
+                  angle_deg)
+
+
+def sawtooth(n_steps: int, amp: float, steps_per_period: int, angle_deg: float):
+    """Field rising linearly from -amp to +amp over each period, then
+    dropping back: amp * (2 (t mod P) / (P - 1) - 1) along a fixed angle."""
+    P = int(steps_per_period)
+    t = np.arange(int(n_steps)) % P
+    return _along(amp * (2.0 * t / max(1, P - 1) - 1.0), angle_deg)
+
+
 def rotating(n_steps: int, amp: float, steps_per_rev: int, phase_deg: float = 0.0):
     """Field of fixed strength whose angle advances 2*pi/steps_per_rev per step."""
     t = np.arange(int(n_steps), dtype=np.float64)

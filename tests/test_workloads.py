@@ -163,3 +163,15 @@ def test_square_vertices_groups():
         assert np.allclose(np.hypot(*(xy[members] - vxy[g]).T), 0.5)
         inner = 0 < vxy[g, 0] < n and 0 < vxy[g, 1] < n
         assert len(members) == (4 if inner else len(members)) and 2 <= len(members) <= 4
+
+
+def test_sinusoidal_and_sawtooth_protocols():
+    H = W.sinusoidal(40, 0.1, 20, 30.0)
+    assert H.shape == (40, 2)
+    strength = H @ np.array([np.cos(np.radians(30)), np.sin(np.radians(30))])
+    assert abs(strength[5] - 0.1) < 1e-15 and abs(strength[15] + 0.1) < 1e-15
+    assert np.allclose(strength[:20], strength[20:])
+    S = W.sawtooth(25, 0.2, 5, 0.0)
+    assert np.allclose(S[:, 1], 0.0)
+    assert S[0, 0] == -0.2 and S[4, 0] == 0.2 and S[5, 0] == -0.2
+    assert np.all(np.diff(S[:5, 0]) > 0)
