@@ -164,6 +164,55 @@ def bench_plain(args, asi, workloads, torch):
     return out
 
 
+def bench_analysis(args, asi, workloads, torch):
+    """The analyses after the path on paper-scale states: the net
+    magnetisation and the spin-spin correlation of the 1M-magnet kagome,
+    vertex maps of a 981,400-magnet closed square.  Wall time per call
+    (each call copies its result to the host and synchronises); the kernel
+    durations come from a kernel trace of this mode."""
+    out = {"metric": "analysis calls/s", "unit": "calls/s", "n_gpus": 1, "data": "synthetic",
+           "dtype": "f64", "higher_is_better": True, "vs_baseline": None}
+    w = workloads.kagome_1m_rotating(n_steps=2)
+    sim = asi.Sim.from_workload(w)
+    rng = np.random.default_rng(3)
+    sim.set_state(rng.choice([-1, 1], w.n).astype(np.int8), -1)
+    reps = 50
+    sim.magnetization()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.magnetization()
+    t_mag = (time.perf_counter() - t0) / reps
+    sim.spin_correlation(w.xy, 0.25, 13)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        sums, cnts = sim.spin_correlation(w.xy, 0.25, 13)
+    t_corr = (time.perf_counter() - t0) / 5
+    info = sim.info()
+    sim.close()
+    xy, theta = workloads.square_closed(700)
+    n = len(theta)
+    sq = workloads.Workload("square700", xy, theta, np.ones(n, np.int8), np.full(n, 0.2),
+                            np.zeros((2, 2)), alpha=0.001, neighbor_distance=1.0, b=1, c=1,
+                            beta=3, gamma=3)
+    ptr, idx, _ = workloads.square_vertices(700)
+    s2 = asi.Sim.from_workload(sq)
+    s2.set_state(rng.choice([-1, 1], n).astype(np.int8), -1)
+    s2.group_magnetization(ptr, idx)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        s2.group_magnetization(ptr, idx)
+    t_vx = (time.perf_counter() - t0) / 5
+    s2.close()
+    out.update({"value": 1.0 / t_mag, "steps": reps, "warmup": 1, "ms_per_step": t_mag * 1e3,
+                "scaling": "weak",
+                "config": {"workload": "kagome577 (998,787 magnets) + square700 (981,400)",
+                           "neighbour_pairs": info["n_edges"], "vertices": len(ptr) - 1},
+                "magnetization_ms": t_mag * 1e3, "correlation_ms": t_corr * 1e3,
+                "correlation_pairs": int(cnts.sum()), "vertex_map_ms": t_vx * 1e3})
+    return out
+
+
 def bench_batched(args, asi, workloads, torch):
     """Uneven sweep of instances: one batched run (one field launch and one
     relax launch per step, replayed from a captured graph) against the same
@@ -314,7 +363,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--mode", choices=["plain", "batched", "served"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batched", "served", "analysis"], default="plain")
     ap.add_argument("--workload", default="kagome577_rotating")
     ap.add_argument("--local-field", default="none", choices=["none", "gradient", "wave"],
                     help="plain: add a static spatial field, or a travelling wave "
@@ -344,7 +393,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    fn = {"plain": bench_plain, "batched": bench_batched, "served": bench_served}[args.mode]
+    fn = {"plain": bench_plain, "batched": bench_batched, "served": bench_served,
+          "analysis": bench_analysis}[args.mode]
     print(json.dumps(fn(args, asi, workloads, torch)), flush=True)
 
 
