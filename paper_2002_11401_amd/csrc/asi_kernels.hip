@@ -2038,9 +2038,12 @@ k_corr(const InstDev* __restrict__ I, const double* __restrict__ xy, double w, i
        i += (int64_t)gridDim.x * blockDim.x) {
     const double xi = xy[2 * i], yi = xy[2 * i + 1];
     const int si = I->s[i];
-    for (int64_t k = 0; k < D; ++k) {
-      const int32_t j = I->rcol[i * D + k];
-      if (j < 0) break;
+    const int32_t L = I->len[i];
+    // the sliced tables: slot k of 64 consecutive rows is contiguous, so
+    // the lanes of a wavefront (consecutive rows) load it together
+    for (int32_t k = 0; k < L; ++k) {
+      const int64_t sl = slot_of(i, (int32_t)D, k);
+      const int32_t j = I->col[sl];
       if (j <= i) continue;
       const double dx = __dsub_rn(xi, xy[2 * (int64_t)j]);
       const double dy = __dsub_rn(yi, xy[2 * (int64_t)j + 1]);
@@ -2048,7 +2051,7 @@ k_corr(const InstDev* __restrict__ I, const double* __restrict__ xy, double w, i
       const double q = floor(__ddiv_rn(r, w));
       if (!(q < (double)nbins)) continue;
       const int b = (int)q;
-      const double a = I->rA[i * D + k];
+      const double a = I->A[sl];
       int c = 0;
       if (fabs(a) > 1e-9 * abs_alpha / (r * r * r)) c = ((si * I->s[j]) * (a > 0.0 ? 1 : -1) > 0) ? 1 : -1;
       atomicAdd(&bs[b], c);
