@@ -350,9 +350,9 @@ class Sim:
         if len(ptr) < 2 or ptr[-1] > len(idx):
             raise ValueError("ptr must have G+1 entries ending at most at len(idx)")
         out = np.zeros((len(ptr) - 1, 2))
+        idx_buf = idx if len(idx) else np.zeros(1, np.int32)   # held across the call
         _check(library().asi_group_magnetization(self.handle, len(ptr) - 1, _ptr(ptr),
-                                                 _ptr(idx if len(idx) else np.zeros(1, np.int32)),
-                                                 _ptr(out)))
+                                                 _ptr(idx_buf), _ptr(out)))
         return out
 
     def set_magnetization_log(self, on: bool = True):
