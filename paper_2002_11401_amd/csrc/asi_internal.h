@@ -98,7 +98,7 @@ struct RunDev {
   int64_t t;          // step the next field pass evaluates (-1: no field)
   int64_t t_end;      // run stops before this step
   int32_t active;     // instance takes part in the next launch
-  int32_t status;     // 0, or ASI_ELOOP
+  int32_t status;     // 0, ASI_ELOOP or kPoolOverflow
   int64_t flips;      // flips since create / set_state
   int64_t flips_call; // flips since the host last cleared it
   uint64_t hash;      // running flip-log hash
@@ -160,8 +160,13 @@ void launch_relax(const InstDev* insts, RunDev* runs, int32_t count, int32_t wav
 void launch_fused(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
                   size_t lds_bytes, int64_t max_steps, int64_t budget_ticks,
                   int32_t first_ready, hipStream_t st);
-void launch_set_run(RunDev* run, int64_t t, int64_t t_end, int32_t active, int32_t reset_log,
-                    int64_t cur_step, hipStream_t st);
+// Run-cursor update on the stream; with ccount, also empties the
+// instance's candidate pool.
+void launch_set_run(RunDev* run, int32_t* ccount, int64_t t, int64_t t_end, int32_t active,
+                    int32_t reset_log, int64_t cur_step, hipStream_t st);
+// RunDev::status of a step whose candidate pool overflowed its capacity
+// (an internal error: the host reports ASI_EDEVICE).
+constexpr int32_t kPoolOverflow = -3;
 // Dynamic LDS of the relax and fused kernels for an instance of n magnets.
 size_t relax_lds_bytes(int64_t n, int32_t l1_shift);
 int32_t relax_l1_shift(int64_t n);

@@ -444,6 +444,10 @@ __device__ __forceinline__ void pool_put(const InstDev* __restrict__ I, double k
   const int lane = threadIdx.x & 63;
   if (key > 0.0) {
     const int64_t q = base + __popcll(bal & ((1ull << lane) - 1ull));
+    // A pass appends each row at most once to a pool emptied before it, so
+    // q < n < ccap; past the end the entry is dropped and the relax, which
+    // finds the count above ccap, fails the step (kPoolOverflow).
+    if (q >= I->ccap) return;
     const uint32_t i = payload & 0x7fffffffu;
     I->cpay[0][q] = payload;
     I->ckey[0][q] = key;
@@ -1834,11 +1838,15 @@ __device__ __forceinline__ int relax_step(const InstDev* __restrict__ I, RunDev*
   bool spec = blockDim.x == 1024 &&
               (R->paused ? R->spec != 0 : (I->D <= kSpecMaxD && ncand >= I->spec_min));
   int status = 2;
-  if (spec) status = relax_spec(I, t, lds_raw, ssh, ncand, flips, logpos, hash, deadline);
-  if (status == 2) {
-    if (spec) rebuild_t1(I);  // the keys have moved since the field phase
-    spec = false;
-    status = relax_tree(I, t, lds_raw, sh, flips, logpos, hash, deadline);
+  if ((int64_t)(uint32_t)ncand > I->ccap) {
+    status = kPoolOverflow;  // cannot happen while every pass starts from an empty pool
+  } else {
+    if (spec) status = relax_spec(I, t, lds_raw, ssh, ncand, flips, logpos, hash, deadline);
+    if (status == 2) {
+      if (spec) rebuild_t1(I);  // the keys have moved since the field phase
+      spec = false;
+      status = relax_tree(I, t, lds_raw, sh, flips, logpos, hash, deadline);
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1924,9 +1932,10 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_fused(const InstDev* __
 
 // Run-cursor update, launched on the stream so it orders with the kernels
 // (and can sit inside a captured graph).
-__global__ void k_set_run(RunDev* R, int64_t t, int64_t t_end, int32_t active,
+__global__ void k_set_run(RunDev* R, int32_t* ccount, int64_t t, int64_t t_end, int32_t active,
                           int32_t reset_log, int64_t cur_step) {
   if (threadIdx.x != 0) return;
+  if (ccount) *ccount = 0;  // the next field pass starts an empty candidate pool
   R->t = t;
   R->t_end = t_end;
   R->active = active;
@@ -2152,10 +2161,10 @@ void launch_fused(const InstDev* insts, RunDev* runs, int32_t count, int32_t wav
                      max_steps, budget_ticks, first_ready);
 }
 
-void launch_set_run(RunDev* run, int64_t t, int64_t t_end, int32_t active, int32_t reset_log,
-                    int64_t cur_step, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_run, dim3(1), dim3(64), 0, st, run, t, t_end, active, reset_log,
-                     cur_step);
+void launch_set_run(RunDev* run, int32_t* ccount, int64_t t, int64_t t_end, int32_t active,
+                    int32_t reset_log, int64_t cur_step, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_run, dim3(1), dim3(64), 0, st, run, ccount, t, t_end, active,
+                     reset_log, cur_step);
 }
 
 int32_t relax_l1_shift(int64_t n) {

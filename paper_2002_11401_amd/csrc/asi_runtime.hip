@@ -476,7 +476,7 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   HIPCHK(hipMemcpyAsync(s->blk_row0, br.data(), 4 * s->nblocks, hipMemcpyHostToDevice, s->stream),
          s);
   HIPCHK(hipMemcpyAsync(s->dI, &s->hI, sizeof(InstDev), hipMemcpyHostToDevice, s->stream), s);
-  launch_set_run(s->dR, -1, -1, 0, 1, -1, s->stream);
+  launch_set_run(s->dR, I.ccount, -1, -1, 0, 1, -1, s->stream);
   // 16 wavefronts: the speculative relax spreads up to 2048 member and
   // neighbour slots over 1024 lanes; touched tiles are rescanned in parallel
   s->relax_waves = kMaxRelaxWaves;
@@ -519,7 +519,7 @@ asi_status alloc_mag_log(asi_sim* s) {
 }
 
 asi_status run_steps(asi_sim* s, int64_t t0, int64_t t1, int64_t* flips_out) {
-  launch_set_run(s->dR, t0, t1, t0 < t1 ? 1 : 0, 0, 0, s->stream);
+  launch_set_run(s->dR, s->hI.ccount, t0, t1, t0 < t1 ? 1 : 0, 0, 0, s->stream);
   for (int64_t t = t0; t < t1; ++t) {
     field_pass(s);
     relax_pass(s);
@@ -532,6 +532,10 @@ asi_status run_steps(asi_sim* s, int64_t t0, int64_t t1, int64_t* flips_out) {
   if (st != ASI_OK) return st;
   s->cur_step = r.cur_step;
   if (flips_out) *flips_out = r.flips_call;
+  if (r.status == kPoolOverflow) {
+    s->poisoned = true;
+    return fail(ASI_EDEVICE, "candidate pool overflow at step " + std::to_string(r.cur_step));
+  }
   if (r.status == ASI_ELOOP)
     return fail(ASI_ELOOP, "a relax exceeded max_flips_per_step at step " +
                                std::to_string(r.cur_step));
@@ -1004,9 +1008,11 @@ asi_status asi_compute_fields(asi_handle h, int64_t t) {
   asi_status st = check_handle(h);
   if (st != ASI_OK) return st;
   if (t < -1 || t >= h->K) return fail(ASI_EINVAL, "step outside the protocol");
-  launch_set_run(h->dR, t, t + 1, 1, 0, 0, h->stream);
+  launch_set_run(h->dR, h->hI.ccount, t, t + 1, 1, 0, 0, h->stream);
   field_pass(h);
-  launch_set_run(h->dR, t, t, 0, 0, 0, h->stream);
+  // the pass appended every flippable magnet to the candidate pool: empty
+  // it, so that a later relax sees only its own step's entries
+  launch_set_run(h->dR, h->hI.ccount, t, t, 0, 0, 0, h->stream);
   return sync_and_check(h);
 }
 
@@ -1042,7 +1048,7 @@ asi_status asi_set_state(asi_handle h, const int8_t* spins, int64_t step) {
   HIPCHK(hipStreamSynchronize(h->stream), h);
   HIPCHK(hipMemcpyAsync(h->hI.s, spins, h->n, hipMemcpyHostToDevice, h->stream), h);
   HIPCHK(hipMemsetAsync(h->hI.dirty, 1, h->n, h->stream), h);
-  launch_set_run(h->dR, step, step, 0, 1, step, h->stream);
+  launch_set_run(h->dR, h->hI.ccount, step, step, 0, 1, step, h->stream);
   h->cur_step = step;
   return sync_and_check(h);
 }
@@ -1290,7 +1296,7 @@ extern "C" asi_status asi_batch_run(asi_handle* hs, int32_t count, int32_t mode,
       for (int32_t k = 0; k < count; ++k) hs[k]->poisoned = true;
     return res;
   }
-  bool loop = false;
+  bool loop = false, overflow = false;
   for (int32_t k = 0; k < count; ++k) {
     asi_sim* h = hs[k];
     HIPCHK(hipMemcpyAsync(h->dR, &runs[k], sizeof(RunDev), hipMemcpyHostToDevice, h->stream), h);
@@ -1298,7 +1304,12 @@ extern "C" asi_status asi_batch_run(asi_handle* hs, int32_t count, int32_t mode,
     h->cur_step = runs[k].cur_step;
     if (flips_out) flips_out[k] = runs[k].flips_call;
     if (runs[k].status == ASI_ELOOP) loop = true;
+    if (runs[k].status == kPoolOverflow) {
+      h->poisoned = true;
+      overflow = true;
+    }
   }
+  if (overflow) return fail(ASI_EDEVICE, "candidate pool overflow");
   if (loop) return fail(ASI_ELOOP, "an instance exceeded max_flips_per_step");
   return ASI_OK;
 }
@@ -1672,7 +1683,7 @@ asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out
              (asi_sim*)nullptr);
       HIPCHK(hipStreamSynchronize(S->stream), (asi_sim*)nullptr);
       J.state = r.status == 0 ? 2 : 3;
-      J.err = r.status == 0 ? ASI_OK : ASI_ELOOP;
+      J.err = r.status == 0 ? ASI_OK : (r.status == kPoolOverflow ? ASI_EDEVICE : ASI_ELOOP);
       J.t_done = now_s();
       asi_destroy(J.h);
       J.h = nullptr;

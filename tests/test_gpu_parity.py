@@ -340,6 +340,34 @@ def test_library_draws_the_disorder():
         asi.Sim(w.xy, w.theta, None, w.spin0, H=w.H, hk_mean=0.0, **w.params())
 
 
+def test_field_evaluations_leave_no_candidates_behind():
+    """Full-field passes without a relax (asi_compute_fields) at other steps,
+    repeated past the candidate pool's capacity, must not leak their
+    flippable magnets into the next relax: that relax flips exactly what the
+    one-at-a-time relax of Sec. II.H flips, on the speculative path."""
+    xy, theta = W.kagome(30)
+    n = len(theta)
+    H = W.rotating(12, 0.3, 12)
+    w = W.Workload("kagome30_strong", xy, theta, np.ones(n, np.int8),
+                   W.disorder_hk(n, 0.15, 0.05, 9), H, alpha=0.002, neighbor_distance=3.0,
+                   b=1, c=1, beta=3, gamma=3, thermal_std=0.002, thermal_seed=5)
+    say("compute_fields then run", n)
+    sim = gpu_sim(w)
+    t = sim.tuning()
+    sim.set_tuning(t["relax_waves"], t["l1_shift"], 1)   # speculate on every step
+    for k in (5, 3, 7, 0, 9, 11, 2, 6):                  # 8 passes > (n + 8192) / n
+        sim.compute_fields(k)
+    sim.run()
+    o, r = oracle_run(w)
+    assert r["per_step"][0] >= 32
+    assert_same_flips(sim.flip_log(), r, sim.state()[0], o.spins())
+    # again after the run, then a relax at the last step: nothing left to flip
+    sim.compute_fields(3)
+    sim.compute_fields(8)
+    assert sim.relax() == 0
+    assert_same_flips(sim.flip_log(), r, sim.state()[0], o.spins())
+
+
 # ------------------------------------------------------------------ autotuner
 @pytest.mark.parametrize("family,d,thermal", [("kagome", 3, 0.005), ("pinwheel", 8, 0.0),
                                               ("square", 4, 0.003)])
