@@ -17,6 +17,8 @@ SRC = os.path.join(HERE, "relax.cpp")
 LIB = os.path.join(HERE, "liborc.so")
 
 _lib = None
+# FNV-1a 64-bit offset basis: the checksum of an empty flip log
+FNV_OFFSET = 14695981039346656037
 
 
 def build(force: bool = True) -> str:
@@ -50,7 +52,7 @@ def lib():
         L.orc_run.restype = C.c_int
         L.orc_run.argtypes = [P, C.c_int64, dp, C.c_int64, C.c_int64, C.c_void_p,
                               C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.c_void_p,
-                              C.c_void_p, C.c_int64]
+                              C.c_void_p, C.c_int64, C.POINTER(C.c_uint64), C.c_void_p]
         L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_normal_pair.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                       C.c_void_p]
@@ -255,8 +257,12 @@ class Oracle:
         lib().orc_fields(self._h, _dp(H), 0, None, None, _vp(hx), _vp(hy), None)
         return hx, hy
 
-    def run(self, Hs, t_begin=0, t_end=None, log_cap=None, max_flips_per_step=0):
-        """Run steps; returns dict(status, flips (t, j) arrays, per_step, gaps)."""
+    def run(self, Hs, t_begin=0, t_end=None, log_cap=None, max_flips_per_step=0,
+            fnv=FNV_OFFSET):
+        """Run steps; returns dict(status, flips (t, j) arrays, per_step, gaps,
+        hash, step_top2).  `hash` is the FNV-1a checksum of every flip of the
+        call (stored in the log or not), continued from `fnv`; `step_top2`
+        the smallest top-two relative key gap of each step."""
         Hs = np.ascontiguousarray(Hs, dtype=np.float64)
         K = len(Hs)
         t_end = K if t_end is None else int(t_end)
@@ -265,12 +271,16 @@ class Oracle:
         lt = np.zeros(cap, dtype=np.int32)
         lj = np.zeros(cap, dtype=np.int32)
         per = np.zeros(max(1, t_end - t_begin), dtype=np.int32)
+        top2 = np.zeros(max(1, t_end - t_begin))
         gaps = np.zeros(3)
         nf = C.c_int64(0)
+        h = C.c_uint64(int(fnv))
         st = lib().orc_run(self._h, K, _dp(Hs), int(t_begin), t_end, _vp(lt), _vp(lj),
-                           cap, C.byref(nf), _vp(per), _vp(gaps), int(max_flips_per_step))
+                           cap, C.byref(nf), _vp(per), _vp(gaps), int(max_flips_per_step),
+                           C.byref(h), _vp(top2))
         n = nf.value
         return dict(status=int(st), n_flips=n, step=lt[:min(n, cap)].copy(),
                     idx=lj[:min(n, cap)].copy(), truncated=n > cap,
-                    per_step=per[:t_end - t_begin].copy(),
+                    per_step=per[:t_end - t_begin].copy(), hash=h.value,
+                    step_top2=top2[:t_end - t_begin].copy(),
                     gaps=dict(top2_rel=gaps[0], thresh_rel=gaps[1], par_rel=gaps[2]))

@@ -377,15 +377,28 @@ void orc_fields(void* h, const double* H, int64_t t, double* hpar, double* hperp
   }
 }
 
+// Checksum of a flip log, independent of the library's: FNV-1a over one
+// 64-bit word per flip, (uint32 step << 32 | uint32 index): h = (h ^ w) *
+// 1099511628211 mod 2^64, starting from 14695981039346656037.
+inline uint64_t fnv_fold(uint64_t h, int64_t t, int32_t j) {
+  const uint64_t w = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)j;
+  return (h ^ w) * 1099511628211ull;
+}
+
 // Run field steps t_begin .. t_end-1 of the protocol H[K][2] (Sec. II.H).
 // Returns 0, or -5 when a step exceeds max_flips_per_step (0: no cap).
 // Flip log entries beyond log_cap are counted but not stored.
-// gaps (may be NULL) receives {min_top2_rel, min_thresh_rel, min_par_rel}.
+// gaps (may be NULL) receives {min_top2_rel, min_thresh_rel, min_par_rel};
+// step_top2 (may be NULL) the smallest top-two relative gap of each step
+// (+inf where a step never had two candidates).  fnv (may be NULL) is
+// folded with every flip, stored or not.
 int orc_run(void* h, int64_t K, const double* H, int64_t t_begin, int64_t t_end,
             int32_t* log_t, int32_t* log_j, int64_t log_cap, int64_t* n_flips,
-            int32_t* flips_per_step, double* gaps, int64_t max_flips_per_step) {
+            int32_t* flips_per_step, double* gaps, int64_t max_flips_per_step,
+            uint64_t* fnv, double* step_top2) {
   Model& M = *static_cast<Model*>(h);
   Gaps G;
+  uint64_t hsum = fnv ? *fnv : 0ull;
   int64_t count = 0;
   int status = 0;
   std::vector<double> L(M.n, 0.0);
@@ -406,19 +419,21 @@ int orc_run(void* h, int64_t K, const double* H, int64_t t_begin, int64_t t_end,
       if (ev.flip) cand.insert(std::make_pair(-ev.L, (int32_t)i));
     }
     int64_t step_flips = 0;
+    double step_gap = INFINITY;
     while (!cand.empty()) {
       auto top = cand.begin();
       int32_t j = top->second;
       if (cand.size() > 1) {
         auto nxt = std::next(top);
         double l1 = -top->first, l2 = -nxt->first;
-        G.min_top2_rel = std::min(G.min_top2_rel, (l1 - l2) / l1);
+        step_gap = std::min(step_gap, (l1 - l2) / l1);
       }
       cand.erase(top);
       in_set[j] = 0;
       if (max_flips_per_step > 0 && step_flips >= max_flips_per_step) { status = -5; break; }
       M.s[j] = (int8_t)(-M.s[j]);
       if (count < log_cap) { log_t[count] = (int32_t)t; log_j[count] = j; }
+      hsum = fnv_fold(hsum, t, j);
       ++count;
       ++step_flips;
       // fields change exactly on j's neighbours: re-sum them from Eq. 3
@@ -436,8 +451,11 @@ int orc_run(void* h, int64_t K, const double* H, int64_t t_begin, int64_t t_end,
       for (int64_t e = M.nb_ptr[j]; e < M.nb_ptr[j + 1]; ++e) retest(M.nb_idx[e]);
     }
     if (flips_per_step) flips_per_step[t - t_begin] = (int32_t)step_flips;
+    if (step_top2) step_top2[t - t_begin] = step_gap;
+    G.min_top2_rel = std::min(G.min_top2_rel, step_gap);
   }
   if (n_flips) *n_flips = count;
+  if (fnv) *fnv = hsum;
   if (gaps) { gaps[0] = G.min_top2_rel; gaps[1] = G.min_thresh_rel; gaps[2] = G.min_par_rel; }
   return status;
 }
