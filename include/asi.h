@@ -170,6 +170,27 @@ asi_status asi_group_magnetization(asi_handle h, int64_t n_groups, const int64_t
 asi_status asi_spin_correlation(asi_handle h, const double* xy, double bin_width,
                                 int32_t n_bins, int64_t* sum_out, int64_t* count_out);
 
+/* Switching order (Sec. IV.D): pos_out[j] (host int64[n]) receives the
+ * position in the flip log (0-based, counting from create / set_state) of
+ * magnet j's first switch, or the log's length for a magnet that never
+ * switched.  Computed on the device from the flip log.  ASI_ESTATE when
+ * more flips happened than flip_log_capacity keeps. */
+asi_status asi_switching_order(asi_handle h, int64_t* pos_out);
+
+/* Spearman's rank correlation coefficient rho of the switching orders of
+ * two instances of the same n magnets (Sec. IV.D; e.g. the same array at two
+ * lattice spacings, or with and without coupling): the Pearson correlation
+ * of the two vectors of ranks of the asi_switching_order positions, tied
+ * positions (magnets that never switched) sharing their mean rank.  On the
+ * device, exactly: with u_i = 2 rank_i - (n + 1) (an integer), the sums
+ * Sab = sum u_a u_b, Saa = sum u_a^2, Sbb = sum u_b^2 are formed in integer
+ * arithmetic, then rho = Sab / sqrt(Saa * Sbb) in FP64 from the totals
+ * rounded to double (NaN when Saa or Sbb is 0).  sums_out (may be NULL):
+ * int64[6], the three totals as 128-bit two's complement (low, high) pairs.
+ * a == b is allowed (rho = 1 unless every magnet ties).  ASI_EINVAL for
+ * different n or n outside 2 .. 2^27; ASI_ESTATE as asi_switching_order. */
+asi_status asi_switching_rho(asi_handle a, asi_handle b, double* rho_out, int64_t* sums_out);
+
 /* Per-step magnetisation log: while enabled, asi_run and asi_relax record M
  * after the relax of every step t they run into row t of a device array of
  * the protocol's length (rows of steps not run hold NaN; a new protocol
@@ -343,6 +364,22 @@ typedef struct {
 } asi_server_stats;
 asi_status asi_server_get_stats(asi_server_t s, asi_server_stats* out);
 asi_status asi_server_destroy(asi_server_t s);
+
+/* ---- measurement aid (not part of the model) ---------------------------
+ * Latency of dependent global-memory loads, the floor of the relax of Sec.
+ * II.H, whose flips are chains of such loads: lanes 1 .. 64 of one
+ * wavefront each follow a pointer chain through a buffer of `bytes` bytes
+ * (one 4-byte element per 128-byte line, the lines in one random cycle drawn
+ * from `seed`, built and checked on the host; lane l starts l/64 of the way
+ * round), `hops` loads each, timed with the device's constant-rate clock.
+ * With lanes = 1 a hop is one load; with 64 it is one scattered 64-address
+ * gather.  A buffer that fits the L2 (a few MB) gives the L2 latency, one far
+ * beyond the 256 MB last-level cache the HBM latency.  ns_out receives
+ * nanoseconds per hop.  Allocates bytes / 32 bytes through dev (NULL:
+ * hipMalloc on the current device, own stream).  ASI_EINVAL unless hops >=
+ * 1, 1 <= lanes <= 64 and 8 KiB <= bytes <= 2^36. */
+asi_status asi_measure_load_latency(const asi_device* dev, int64_t bytes, int64_t hops,
+                                    int32_t lanes, uint64_t seed, double* ns_out);
 
 #ifdef __cplusplus
 }

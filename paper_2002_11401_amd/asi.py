@@ -96,6 +96,8 @@ SIGNATURES = {
     "asi_magnetization": [P, P],
     "asi_spin_correlation": [P, P, C.c_double, C.c_int32, P, P],
     "asi_group_magnetization": [P, C.c_int64, P, P, P],
+    "asi_switching_order": [P, P],
+    "asi_switching_rho": [P, P, C.POINTER(C.c_double), P],
     "asi_set_magnetization_log": [P, C.c_int32],
     "asi_get_magnetization_log": [P, P],
     "asi_relax": [P, I64P],
@@ -123,6 +125,8 @@ SIGNATURES = {
     "asi_get_tuning": [P, C.POINTER(AsiTuning)],
     "asi_set_tuning": [P, C.POINTER(AsiTuning)],
     "asi_server_destroy": [P],
+    "asi_measure_load_latency": [C.POINTER(AsiDevice), C.c_int64, C.c_int64, C.c_int32,
+                                 C.c_uint64, C.POINTER(C.c_double)],
 }
 
 _lib = None
@@ -355,6 +359,13 @@ class Sim:
                                                  _ptr(idx_buf), _ptr(out)))
         return out
 
+    def switching_order(self) -> np.ndarray:
+        """[n]: flip-log position of each magnet's first switch (the log's
+        length for magnets that never switched), computed on the device."""
+        out = np.zeros(self.n, dtype=np.int64)
+        _check(library().asi_switching_order(self.handle, _ptr(out)))
+        return out
+
     def set_magnetization_log(self, on: bool = True):
         _check(library().asi_set_magnetization_log(self.handle, 1 if on else 0))
 
@@ -444,6 +455,17 @@ class Sim:
                     relax_launches=t.relax_launches, relax_ms=t.relax_ms)
 
 
+def switching_rho(a: Sim, b: Sim):
+    """Spearman's rho of the switching orders of two instances (Sec. IV.D),
+    computed on the device: (rho, (Sab, Saa, Sbb)) with the exact integer
+    sums of the rank products."""
+    rho = C.c_double(0.0)
+    sums = np.zeros(6, dtype=np.int64)
+    _check(library().asi_switching_rho(a.handle, b.handle, C.byref(rho), _ptr(sums)))
+    tot = tuple(int(np.uint64(sums[2 * c])) + (int(sums[2 * c + 1]) << 64) for c in range(3))
+    return rho.value, tot
+
+
 def batch_run(sims: Sequence[Sim], mode: str = "fused"):
     """Run every instance to the end of its own protocol in batched launches
     (mode: 'lockstep', 'graph' or 'fused', see asi_batch_run)."""
@@ -525,3 +547,13 @@ class Server:
         st = AsiServerStats()
         _check(library().asi_server_get_stats(self._h, C.byref(st)))
         return {name: getattr(st, name) for name, _ in AsiServerStats._fields_}
+
+
+def load_latency_ns(nbytes: int, hops: int = 100000, lanes: int = 1, seed: int = 1) -> float:
+    """Nanoseconds per dependent load (lanes = 1) or per dependent 64-lane
+    gather (lanes = 64) over a buffer of nbytes (asi_measure_load_latency)."""
+    dev = make_device("hip")
+    ns = C.c_double(0.0)
+    _check(library().asi_measure_load_latency(C.byref(dev.struct), int(nbytes), int(hops),
+                                              int(lanes), int(seed), C.byref(ns)))
+    return ns.value

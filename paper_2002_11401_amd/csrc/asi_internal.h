@@ -130,6 +130,24 @@ constexpr int kCorrMaxBins = 4096;
 void launch_correlation(const InstDev* inst, int64_t n, const double* xy, double w,
                         int32_t nbins, double abs_alpha, uint64_t* sum, uint64_t* cnt,
                         hipStream_t st);
+// Switching order of a flip log of L entries over n magnets (Sec. IV.D):
+// pos[j] = log position of magnet j's first switch (L if none), r2[j] =
+// twice its average rank in that order (integers; never-switched magnets
+// tie).  scratch: switching_scratch_count(L) int64 on the device.
+int64_t switching_scratch_count(int64_t L);
+void launch_switching_ranks(const int32_t* log_j, int64_t L, int64_t n, unsigned long long* pos,
+                            int64_t* r2, int64_t* scratch, hipStream_t st);
+// Exact partial sums of u_a u_b, u_a^2, u_b^2 (u = r2 - (n + 1)) per block
+// of magnets into part[3 * rank_corr_blocks(n)]; requires n <= 2^27.
+constexpr int64_t kRankCorrMaxN = (int64_t)1 << 27;
+int64_t rank_corr_blocks(int64_t n);
+void launch_rank_correlation(const int64_t* r2a, const int64_t* r2b, int64_t n, long long* part,
+                             hipStream_t st);
+// Pointer chase (measurement): lanes 0 .. lanes-1 (<= 64) of one wavefront
+// each take `hops` dependent loads along chain from starts[lane]; out[0] =
+// elapsed device-clock ticks, out[1 + lane] = each lane's last index.
+void launch_chase(const int32_t* chain, const int32_t* starts, int32_t lanes, int64_t hops,
+                  unsigned long long* out, hipStream_t st);
 void launch_neighbour_count(const double* x, const double* y, const int32_t* cellx,
                             const int32_t* celly, const int32_t* cell_start,
                             const int32_t* cell_members, int64_t n, int64_t gx, int64_t gy,

@@ -2076,9 +2076,213 @@ k_corr(const InstDev* __restrict__ I, const double* __restrict__ xy, double w, i
   }
 }
 
+// Switching order of a flip log (Sec. IV.D): the log position of each
+// magnet's first switch, and the twice-average rank of each magnet in that
+// order.  Switched magnets have distinct first positions; a magnet that
+// never switched is placed after all of them, so those magnets share the
+// ranks S+1 .. n (S = switched magnets) and each gets their mean.  All of it
+// is integer arithmetic: the results do not depend on the order of atomics.
+constexpr int kRankBlock = 1024;  // log entries per block of the rank scan
+
+__global__ void __launch_bounds__(256)
+k_fill_u64(unsigned long long* __restrict__ p, int64_t n, unsigned long long v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// pos[j] = smallest log position k with log_j[k] == j (pos preset to L).
+__global__ void __launch_bounds__(256)
+k_first_switch(const int32_t* __restrict__ log_j, int64_t L, unsigned long long* __restrict__ pos) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < L;
+       k += (int64_t)gridDim.x * blockDim.x)
+    atomicMin(&pos[log_j[k]], (unsigned long long)k);
+}
+
+// Log entry k is a first switch when pos[log_j[k]] == k.  Returns its
+// exclusive rank among the first switches of this block's entries (uniform
+// over the block after the call: wave totals in wtot[16]).
+__device__ __forceinline__ int first_rank_in_block(const int32_t* __restrict__ log_j, int64_t L,
+                                                   const unsigned long long* __restrict__ pos,
+                                                   int* wtot, bool& first, int32_t& j,
+                                                   int& block_total) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t k = (int64_t)blockIdx.x * kRankBlock + tid;
+  first = false;
+  j = 0;
+  if (k < L) {
+    j = log_j[k];
+    first = pos[j] == (unsigned long long)k;
+  }
+  const unsigned long long bal = __ballot(first);
+  if (lane == 0) wtot[wave] = __popcll(bal);
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int w = 0; w < kRankBlock / 64; ++w) {
+    if (w < wave) before += wtot[w];
+    tot += wtot[w];
+  }
+  block_total = tot;
+  return before + __popcll(bal & ((1ull << lane) - 1ull));
+}
+
+__global__ void __launch_bounds__(kRankBlock)
+k_first_count(const int32_t* __restrict__ log_j, int64_t L,
+              const unsigned long long* __restrict__ pos, int64_t* __restrict__ cnt) {
+  __shared__ int wtot[kRankBlock / 64];
+  bool first;
+  int32_t j;
+  int tot;
+  (void)first_rank_in_block(log_j, L, pos, wtot, first, j, tot);
+  if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the nb block counts by one workgroup (chunks of 1024
+// with a running carry); total[0] = number of switched magnets.
+__global__ void __launch_bounds__(kRankBlock)
+k_scan_counts(const int64_t* __restrict__ cnt, int64_t nb, int64_t* __restrict__ off,
+              int64_t* __restrict__ total) {
+  __shared__ int64_t buf[kRankBlock];
+  __shared__ int64_t carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < nb; c0 += kRankBlock) {
+    const int64_t v = (c0 + tid < nb) ? cnt[c0 + tid] : 0;
+    buf[tid] = v;
+    __syncthreads();
+    for (int d = 1; d < kRankBlock; d <<= 1) {  // inclusive Hillis-Steele scan
+      const int64_t add = tid >= d ? buf[tid - d] : 0;
+      __syncthreads();
+      buf[tid] += add;
+      __syncthreads();
+    }
+    if (c0 + tid < nb) off[c0 + tid] = carry + buf[tid] - v;
+    __syncthreads();
+    if (tid == 0) carry += buf[kRankBlock - 1];
+    __syncthreads();
+  }
+  if (tid == 0) total[0] = carry;
+}
+
+// Every magnet first gets the mean rank of the never-switched group,
+// 2r = S + 1 + n; then each first switch overwrites its magnet's value.
+__global__ void __launch_bounds__(256)
+k_rank_rest(int64_t* __restrict__ r2, int64_t n, const int64_t* __restrict__ total) {
+  const int64_t v = total[0] + 1 + n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    r2[i] = v;
+}
+
+__global__ void __launch_bounds__(kRankBlock)
+k_rank_switched(const int32_t* __restrict__ log_j, int64_t L,
+                const unsigned long long* __restrict__ pos, const int64_t* __restrict__ off,
+                int64_t* __restrict__ r2) {
+  __shared__ int wtot[kRankBlock / 64];
+  bool first;
+  int32_t j;
+  int tot;
+  const int r = first_rank_in_block(log_j, L, pos, wtot, first, j, tot);
+  if (first) r2[j] = 2 * (off[blockIdx.x] + r + 1);
+}
+
+// Pearson correlation of two rank vectors from exact sums: with u = 2r -
+// (n + 1) per magnet, one block adds u_a u_b, u_a^2 and u_b^2 of its 256
+// magnets into part[3 b .. 3 b + 2] (each |u| < n <= 2^27, so a block sum
+// stays below 2^62).
+constexpr int kCorrRankThreads = 256;
+
+__global__ void __launch_bounds__(kCorrRankThreads)
+k_rank_corr(const int64_t* __restrict__ r2a, const int64_t* __restrict__ r2b, int64_t n,
+            long long* __restrict__ part) {
+  __shared__ long long sab[kCorrRankThreads], saa[kCorrRankThreads], sbb[kCorrRankThreads];
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kCorrRankThreads + tid;
+  long long ua = 0, ub = 0;
+  if (i < n) {
+    ua = (long long)(r2a[i] - (n + 1));
+    ub = (long long)(r2b[i] - (n + 1));
+  }
+  sab[tid] = ua * ub;
+  saa[tid] = ua * ua;
+  sbb[tid] = ub * ub;
+  __syncthreads();
+  for (int w = kCorrRankThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      sab[tid] += sab[tid + w];
+      saa[tid] += saa[tid + w];
+      sbb[tid] += sbb[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    part[3 * blockIdx.x] = sab[0];
+    part[3 * blockIdx.x + 1] = saa[0];
+    part[3 * blockIdx.x + 2] = sbb[0];
+  }
+}
+
+// ------------------------------------------------------------ measurement
+// Dependent-load latency: each of the first `lanes` lanes of one wavefront
+// follows a chain of indices from its own start (each load's address comes
+// from the previous load), `hops` times; lane 0 records the elapsed ticks of
+// the device's constant-rate clock.  With 64 lanes a hop is one scattered
+// 64-address gather, the unit of work of the relax's neighbour updates.  The
+// chain is built and checked on the host to be one cycle over the buffer,
+// so every load is in bounds however many hops are taken.
+__global__ void k_chase(const int32_t* __restrict__ chain, const int32_t* __restrict__ starts,
+                        int32_t lanes, int64_t hops, unsigned long long* __restrict__ out) {
+  const int lane = threadIdx.x;
+  if (blockIdx.x != 0 || lane >= lanes) return;
+  int32_t p = starts[lane];
+  const uint64_t t0 = wall_clock64();
+  for (int64_t h = 0; h < hops; ++h) p = chain[p];
+  const uint64_t t1 = wall_clock64();
+  if (lane == 0) out[0] = t1 - t0;
+  out[1 + lane] = (unsigned long long)p;  // keeps every chain live
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
+void launch_chase(const int32_t* chain, const int32_t* starts, int32_t lanes, int64_t hops,
+                  unsigned long long* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_chase, dim3(1), dim3(64), 0, st, chain, starts, lanes, hops, out);
+}
+
+int64_t switching_scratch_count(int64_t L) {
+  const int64_t nb = std::max<int64_t>(1, (L + kRankBlock - 1) / kRankBlock);
+  return 2 * nb + 1;
+}
+
+void launch_switching_ranks(const int32_t* log_j, int64_t L, int64_t n, unsigned long long* pos,
+                            int64_t* r2, int64_t* scratch, hipStream_t st) {
+  const int64_t nb = std::max<int64_t>(1, (L + kRankBlock - 1) / kRankBlock);
+  const unsigned gn = (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, (n + 255) / 256));
+  const unsigned gl = (unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, (L + 255) / 256));
+  int64_t* cnt = scratch;
+  int64_t* off = scratch + nb;
+  int64_t* total = scratch + 2 * nb;
+  hipLaunchKernelGGL(k_fill_u64, dim3(gn), dim3(256), 0, st, pos, n, (unsigned long long)L);
+  if (L > 0)
+    hipLaunchKernelGGL(k_first_switch, dim3(gl), dim3(256), 0, st, log_j, L, pos);
+  hipLaunchKernelGGL(k_first_count, dim3((unsigned)nb), dim3(kRankBlock), 0, st, log_j, L, pos,
+                     cnt);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kRankBlock), 0, st, cnt, nb, off, total);
+  hipLaunchKernelGGL(k_rank_rest, dim3(gn), dim3(256), 0, st, r2, n, total);
+  hipLaunchKernelGGL(k_rank_switched, dim3((unsigned)nb), dim3(kRankBlock), 0, st, log_j, L, pos,
+                     off, r2);
+}
+
+int64_t rank_corr_blocks(int64_t n) { return (n + kCorrRankThreads - 1) / kCorrRankThreads; }
+
+void launch_rank_correlation(const int64_t* r2a, const int64_t* r2b, int64_t n, long long* part,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_rank_corr, dim3((unsigned)rank_corr_blocks(n)), dim3(kCorrRankThreads), 0,
+                     st, r2a, r2b, n, part);
+}
+
 void launch_correlation(const InstDev* inst, int64_t n, const double* xy, double w,
                         int32_t nbins, double abs_alpha, uint64_t* sum, uint64_t* cnt,
                         hipStream_t st) {

@@ -783,6 +783,105 @@ asi_status asi_group_magnetization(asi_handle h, int64_t n_groups, const int64_t
   return rs;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device allocations of one call, released on every return path.
+struct Scratch {
+  DevMem* mem;
+  std::vector<void*> ptrs;
+  explicit Scratch(DevMem* m) : mem(m) {}
+  template <class T>
+  T* get(size_t count) {
+    void* p = mem->alloc(sizeof(T) * std::max<size_t>(count, 1));
+    if (p) ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  ~Scratch() {
+    for (void* p : ptrs) mem->release(p);
+  }
+};
+
+// First-switch positions and twice-average ranks of the handle's flip log
+// (Sec. IV.D), on the handle's stream, into pos and r2 (device, n each).
+asi_status switching_ranks(asi_sim* h, Scratch& sc, unsigned long long*& pos, int64_t*& r2) {
+  RunDev r{};
+  asi_status st = read_run(h, &r);
+  if (st != ASI_OK) return st;
+  if (r.flips > h->hI.log_cap)
+    return fail(ASI_ESTATE, "the flip log holds " + std::to_string(h->hI.log_cap) + " of " +
+                                std::to_string(r.flips) +
+                                " flips: raise flip_log_capacity to compare switching orders");
+  const int64_t L = r.flips;
+  pos = sc.get<unsigned long long>(h->n);
+  r2 = sc.get<int64_t>(h->n);
+  int64_t* tmp = sc.get<int64_t>(switching_scratch_count(L));
+  if (!pos || !r2 || !tmp) return fail(ASI_ENOMEM, "device allocation failed (switching order)");
+  launch_switching_ranks(h->hI.log_j, L, h->n, pos, r2, tmp, h->stream);
+  HIPCHK(hipGetLastError(), h);
+  return ASI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+asi_status asi_switching_order(asi_handle h, int64_t* pos_out) {
+  asi_status st = check_handle(h);
+  if (st != ASI_OK) return st;
+  if (!pos_out) return fail(ASI_EINVAL, "pos_out is NULL");
+  Scratch sc(&h->mem);
+  unsigned long long* pos = nullptr;
+  int64_t* r2 = nullptr;
+  st = switching_ranks(h, sc, pos, r2);
+  if (st != ASI_OK) return st;
+  HIPCHK(hipMemcpyAsync(pos_out, pos, 8 * h->n, hipMemcpyDeviceToHost, h->stream), h);
+  return sync_and_check(h);
+}
+
+asi_status asi_switching_rho(asi_handle a, asi_handle b, double* rho_out, int64_t* sums_out) {
+  asi_status st = check_handle(a);
+  if (st == ASI_OK) st = check_handle(b);
+  if (st != ASI_OK) return st;
+  if (!rho_out) return fail(ASI_EINVAL, "rho_out is NULL");
+  if (a->n != b->n) return fail(ASI_EINVAL, "the two instances differ in size");
+  if (a->n < 2 || a->n > kRankCorrMaxN) return fail(ASI_EINVAL, "n must be in 2 .. 2^27");
+  const int64_t n = a->n;
+  Scratch sa(&a->mem), sb(&b->mem);
+  unsigned long long *pa = nullptr, *pb = nullptr;
+  int64_t *ra = nullptr, *rb = nullptr;
+  st = switching_ranks(a, sa, pa, ra);
+  if (st == ASI_OK && b != a) st = switching_ranks(b, sb, pb, rb);
+  if (st != ASI_OK) return st;
+  if (b == a) rb = ra;
+  // b's ranks are read on a's stream
+  st = sync_and_check(b);
+  if (st != ASI_OK) return st;
+  const int64_t nb = rank_corr_blocks(n);
+  long long* part = sa.get<long long>(3 * nb);
+  if (!part) return fail(ASI_ENOMEM, "device allocation failed (rank correlation)");
+  launch_rank_correlation(ra, rb, n, part, a->stream);
+  HIPCHK(hipGetLastError(), a);
+  std::vector<long long> hp(3 * nb);
+  HIPCHK(hipMemcpyAsync(hp.data(), part, 8 * 3 * nb, hipMemcpyDeviceToHost, a->stream), a);
+  st = sync_and_check(a);
+  if (st != ASI_OK) return st;
+  // exact totals (|sum| < n^3 < 2^81), then rho in FP64 from the rounded totals
+  __int128 sum[3] = {0, 0, 0};
+  for (int64_t k = 0; k < nb; ++k)
+    for (int c = 0; c < 3; ++c) sum[c] += (__int128)hp[3 * k + c];
+  const double sab = (double)sum[0], saa = (double)sum[1], sbb = (double)sum[2];
+  const double den = std::sqrt(saa * sbb);
+  *rho_out = den > 0.0 ? sab / den : std::nan("");
+  if (sums_out)
+    for (int c = 0; c < 3; ++c) {
+      sums_out[2 * c] = (int64_t)(uint64_t)sum[c];                  // low 64 bits
+      sums_out[2 * c + 1] = (int64_t)(uint64_t)(sum[c] >> 64);      // high 64 bits (signed)
+    }
+  return ASI_OK;
+}
+
 asi_status asi_set_magnetization_log(asi_handle h, int32_t enable) {
   asi_status st = check_handle(h);
   if (st != ASI_OK) return st;
@@ -1701,6 +1800,89 @@ asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out
     *active_out = a;
   }
   return ASI_OK;
+}
+
+asi_status asi_measure_load_latency(const asi_device* dev, int64_t bytes, int64_t hops,
+                                    int32_t lanes, uint64_t seed, double* ns_out) {
+  if (!ns_out || hops < 1 || lanes < 1 || lanes > 64 || bytes < 128 * 64 ||
+      bytes > ((int64_t)1 << 36))
+    return fail(ASI_EINVAL, "need ns_out, hops >= 1, 1 <= lanes <= 64 and 8 KiB <= bytes <= 2^36");
+  // one element per 128-byte line, the lines visited in a random cycle
+  const int64_t lines = bytes / 128;
+  if (lines * 32 > (int64_t)0x7fffffff) return fail(ASI_EINVAL, "buffer too large");
+  std::vector<int32_t> order(lines);
+  for (int64_t k = 0; k < lines; ++k) order[k] = (int32_t)k;
+  uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
+  for (int64_t k = lines - 1; k > 0; --k) {  // Fisher-Yates with a 64-bit LCG
+    x = x * 6364136223846793005ull + 1442695040888963407ull;
+    const int64_t r = (int64_t)((x >> 11) % (uint64_t)(k + 1));
+    std::swap(order[k], order[r]);
+  }
+  // start at line 0: rotate the cycle so that it begins there
+  const int64_t z = std::find(order.begin(), order.end(), 0) - order.begin();
+  std::rotate(order.begin(), order.begin() + z, order.end());
+  std::vector<int32_t> chain((size_t)lines * 32, 0);
+  for (int64_t k = 0; k < lines; ++k)
+    chain[(size_t)order[k] * 32] = order[(k + 1) % lines] * 32;
+  // check: one cycle through every line, every target in bounds
+  {
+    std::vector<char> seen(lines, 0);
+    int64_t p = 0;
+    for (int64_t k = 0; k < lines; ++k) {
+      if (p < 0 || p >= lines * 32 || (p % 32) != 0 || seen[p / 32])
+        return fail(ASI_EDEVICE, "pointer chain is not one cycle");
+      seen[p / 32] = 1;
+      p = chain[(size_t)p];
+    }
+    if (p != 0) return fail(ASI_EDEVICE, "pointer chain is not one cycle");
+  }
+  // lane l starts l/64 of the way round the cycle
+  std::vector<int32_t> starts(64);
+  for (int l = 0; l < 64; ++l) starts[l] = order[(size_t)(l * lines / 64)] * 32;
+  DevMem mem;
+  if (dev) mem.dev = *dev;
+  hipStream_t st = nullptr;
+  bool own = false;
+  if (dev && dev->stream) {
+    st = (hipStream_t)dev->stream;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), (asi_sim*)nullptr);
+    own = true;
+  }
+  mem.st = st;
+  asi_status rs = ASI_OK;
+  int32_t* dchain = static_cast<int32_t*>(mem.alloc(4 * chain.size()));
+  int32_t* dstarts = static_cast<int32_t*>(mem.alloc(4 * 64));
+  unsigned long long* dout = static_cast<unsigned long long*>(mem.alloc(8 * 65));
+  unsigned long long out[65] = {0};
+  hipError_t e = (dchain && dstarts && dout) ? hipSuccess : hipErrorOutOfMemory;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dchain, chain.data(), 4 * chain.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dstarts, starts.data(), 4 * 64, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    // a first pass over (up to) the whole cycle warms caches and translations
+    launch_chase(dchain, dstarts, lanes, std::min<int64_t>(hops, lines), dout, st);
+    launch_chase(dchain, dstarts, lanes, hops, dout, st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 8 * 65, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  int dev_id = 0, khz = 0;
+  if (e == hipSuccess) e = hipGetDevice(&dev_id);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev_id);
+  if (e == hipErrorOutOfMemory && !(dchain && dstarts && dout))
+    rs = fail(ASI_ENOMEM, "device allocation failed (pointer chase)");
+  else if (e != hipSuccess)
+    rs = fail(ASI_EDEVICE, std::string("pointer chase: ") + hipGetErrorString(e));
+  else if (khz <= 0)
+    rs = fail(ASI_EDEVICE, "device clock rate unknown");
+  else
+    *ns_out = (double)out[0] / ((double)khz * 1e3) * 1e9 / (double)hops;
+  (void)hipStreamSynchronize(st);
+  mem.release_all();
+  if (own) (void)hipStreamDestroy(st);
+  return rs;
 }
 
 asi_status asi_server_get_stats(asi_server_t S, asi_server_stats* out) {

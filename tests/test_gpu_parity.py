@@ -852,6 +852,57 @@ def test_spin_correlation_bit_exact():
 
 
 # ------------------------------------------------------------------ edge cases
+def test_switching_order_rho_on_device():
+    """Switching orders and their Spearman rho (Sec. IV.D) from the device
+    flip logs, against the oracle's comparison of the oracle's own logs:
+    first-switch positions equal, the exact rank sums equal, rho equal bit
+    for bit.  A weakly coupled 4 x 4 square against the same array without
+    coupling (every magnet switches), and two thermal seeds of a 19,200-magnet
+    kagome over part of a rotation (the magnets that never switch tie)."""
+    from oracle import switching as S
+    xy, theta = W.square_closed(4)
+    n = len(theta)
+    hk = W.disorder_hk(n, 0.2, 0.05, 9)
+    H = W.linear_ramp(3000, 0.0, 0.3, 224.0)
+    cases = []
+    for alpha in (0.0, 1e-5, 0.02):
+        w = W.Workload(f"square4_a{alpha}", xy, theta, np.ones(n, np.int8), hk, H, alpha=alpha,
+                       neighbor_distance=10.0, b=0.38, c=1.0, beta=1.5, gamma=3.2)
+        cases.append(w)
+    kxy, kth = W.kagome(80)
+    kH = W.rotating(400, 0.08, 400)[:230]
+    kag = [W.Workload(f"kagome80_seed{sd}", kxy, kth, W.polarised_spins(kth, kH[0]),
+                      W.disorder_hk(len(kth), 0.15, 0.05, 2), kH, alpha=0.002,
+                      neighbor_distance=3.0, b=1, c=1, beta=3, gamma=3, thermal_std=0.005,
+                      thermal_seed=sd) for sd in (2, 3)]
+    for pair in ((cases[0], cases[1]), (cases[0], cases[2]), (kag[0], kag[1])):
+        sims, logs = [], []
+        for w in pair:
+            say("switching order", w.name, w.n, w.thermal_seed)
+            sim = gpu_sim(w)
+            sim.run()
+            o, r = oracle_run(w, log_cap=10 ** 7)
+            assert not r["truncated"]
+            pos = sim.switching_order()
+            assert np.array_equal(pos, S.first_switch_positions(r["idx"], w.n))
+            sims.append(sim)
+            logs.append(r["idx"])
+        rho, sums = asi.switching_rho(sims[0], sims[1])
+        rho_o, sums_o = S.switching_rho(logs[0], logs[1], pair[0].n)
+        say("rho", rho, sums)
+        assert sums == sums_o
+        assert rho == rho_o
+        assert asi.switching_rho(sims[1], sims[1])[0] == 1.0
+    assert S.switching_rho(logs[0], logs[1], kag[0].n)[0] < 1.0
+    # sizes must match; a truncated log cannot be ranked
+    with pytest.raises(asi.AsiError):
+        asi.switching_rho(sims[0], gpu_sim(cases[0]))
+    short = gpu_sim(cases[1], flip_log_capacity=5)
+    short.run()
+    with pytest.raises(asi.AsiError):
+        short.switching_order()
+
+
 def test_single_magnet_and_no_neighbours():
     say("single magnet")
     w = W.Workload("one", np.array([[0.0, 0.0]]), np.array([0.0]), np.ones(1, np.int8),
