@@ -2,14 +2,24 @@
 
 A step is one field step of the workload's protocol: a full-field pass over
 every magnet (dipolar gather of all neighbour pairs, applied and thermal
-field, switching keys) followed by the relax to stability.  The default
-workload is the ~1.0M-magnet kagome lattice (577 x 577 cells, neighbour
-distance 3, thermal std 0.005, rotating field of 0.08, 1000 steps per
-revolution): its neighbour tables (~690 MB per pass) exceed the 256 MB
-Infinity Cache, so the full-field pass is measured against HBM.
+field, switching keys) followed by the relax to stability.
 
-Prints one JSON line.  value = neighbour interactions/s of the whole job:
-E (directed neighbour pairs) x steps / wall time, with the relax included.
+Default (--mode all), three phases, one JSON line:
+  1. the ~1.0M-magnet kagome lattice (577 x 577 cells, neighbour distance 3,
+     thermal std 0.005, rotating field of 0.08, 1000 steps per revolution):
+     W warm-up steps, the whole 2000-step protocol timed once
+     (`full_protocol`), then the timed window of K steps whose flips per step
+     are nearest the protocol's mean, reached by an untimed prefix.  value =
+     neighbour interactions/s of the window, E x K / wall time, relax
+     included; `roofline` is the full-field pass of the window (its tables,
+     ~690 MB per pass, exceed the 256 MB Infinity Cache); `cpu_baseline` the
+     single-threaded oracle on the same workload;
+  2. `batched`: the 256-instance sweep, 500 steps, one fused batched launch
+     against 256 sequential plain runs, bitwise compared;
+  3. `served`: the 2000-job Poisson stream through the continuous-batching
+     server in real time (runs/s, p50/p99 latency), against a sample of the
+     jobs re-run alone, bitwise compared.
+--mode plain / batched / served / analysis runs one phase alone.
 """
 from __future__ import annotations
 
@@ -68,36 +78,86 @@ def recorded_traffic():
     return None
 
 
-def cpu_baseline(w, target_s: float = 15.0):
-    """The C++ oracle (single thread) on the first steps of the same
-    workload, until about target_s seconds of CPU work."""
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(w, a, K, spins_a, gpu_window, reps: int = 3):
+    """The C++ oracle, single-threaded, on the same workload: (1) one full
+    field evaluation (every row's Eq. 3 sum, then Eq. 2 projected for every
+    magnet at step a), the oracle's counterpart of one full-field pass, in
+    neighbour interactions/s; (2) flips/s over the GPU's timed window
+    [a, a + K), started from the GPU's state at its start, with its flips
+    checked against the GPU's."""
     from oracle import native
+    t_build = time.perf_counter()
     o = native.Oracle.from_workload(w)
+    t_build = time.perf_counter() - t_build
     E = o.num_edges
-    o.set_spins(w.spin0)
-    steps = 0
+    evals = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        o.set_spins(spins_a)
+        o.fields(w.H, a)
+        evals.append(time.perf_counter() - t0)
+    t_eval = float(np.median(evals))
+    o.set_spins(spins_a)
     t0 = time.perf_counter()
-    flips = 0
-    while time.perf_counter() - t0 < target_s and steps < w.n_steps:
-        r = o.run(w.H, steps, steps + 1)
-        flips += r["n_flips"]
-        steps += 1
+    r = o.run(w.H, a, a + K, log_cap=1024)
     dt = time.perf_counter() - t0
     o.close()
-    return dict(value=E * steps / dt, unit="neighbour interactions/s", cores=1, kind="oracle",
-                sample=f"first {steps} of {w.n_steps} field steps of {w.name} "
-                       f"({flips} flips, {dt:.1f} s, single-threaded C++ oracle)",
-                flips_per_s=flips / dt)
+    same = (r["n_flips"] == gpu_window["flips"] and r["hash"] == gpu_window["hash"])
+    return dict(value=E / t_eval, unit="neighbour interactions/s", cores=1, kind="oracle",
+                sample=(f"{w.name}: one full field evaluation at step {a} (median of {reps}, "
+                        f"{t_eval:.3f} s), then the GPU's window of steps {a}..{a + K - 1} "
+                        f"from the GPU's state ({r['n_flips']} flips, {dt:.1f} s); "
+                        f"single-threaded C++ oracle"),
+                field_calcs_per_s=w.n / t_eval, full_evaluation_s=t_eval,
+                flips_per_s=r["n_flips"] / dt, window_flips=int(r["n_flips"]),
+                window_seconds=dt, window_flips_equal_gpu=bool(same),
+                oracle_build_s=t_build, host=host_info())
+
+
+def representative_window(per_step, K):
+    """First step of the K consecutive steps whose mean flips per step is
+    nearest the whole run's mean (the earliest such window)."""
+    ps = np.asarray(per_step, dtype=np.float64)
+    if K >= len(ps):
+        return 0
+    c = np.convolve(ps, np.ones(K) / K, mode="valid")
+    return int(np.argmin(np.abs(c - ps.mean())))
+
+
+def latency_reference(asi):
+    """Dependent-load latencies of the device (see asi_measure_load_latency):
+    one lane and a 64-lane gather, in the L2 (4 MiB) and in HBM (1 GiB)."""
+    out = {}
+    for label, nbytes in (("l2_4MiB", 4 << 20), ("hbm_1GiB", 1 << 30)):
+        for lanes in (1, 64):
+            out[f"{label}_lanes{lanes}_ns"] = asi.load_latency_ns(nbytes, hops=20000, lanes=lanes)
+    return out
 
 
 def bench_plain(args, asi, workloads, torch):
+    """One instance, full-field pass every step: W warm-up steps, then the
+    whole protocol timed once (full_protocol), then the timed window of K
+    steps (value): the K consecutive steps whose flips per step are nearest
+    the whole run's mean, reached by an untimed prefix of the protocol."""
     w = workloads.NAMED[args.workload]()
     if args.local_field == "gradient":
         # static spatial field on top of the global one (Sec. II.D): a
         # gradient along x, 0.02 from the centre to the edge, at 200 deg
         span = float(np.ptp(w.xy[:, 0])) / 2
         w.h_loc = workloads.spatial_gradient(w.xy, 0.02 / span, 200.0, 0.0)
-    K = w.n_steps if args.steps is None else min(args.steps, w.n_steps)
+    K = min(20 if args.steps is None else args.steps, w.n_steps)
     # every step re-gathers every row: the measured full-field pass
     sim = asi.Sim.from_workload(w, field_mode="full")
     if args.local_field == "wave":
@@ -106,27 +166,67 @@ def bench_plain(args, asi, workloads, torch):
         sim.set_local_wave(w.xy, 0.02, 1.0 / 40.0, 0.0, 500.0, 0.0, 200.0)
     info = sim.info()
     E, N = info["n_edges"], info["n"]
-    # warmup: the first steps, then back to the start state
-    W = min(args.warmup, w.n_steps)
-    if W > 0:
-        sim.run(0, W)
+    Wu = min(args.warmup, w.n_steps)
+    if Wu > 0:
+        sim.run(0, Wu)
+    progress(f"{w.name}: {N} magnets, {E} pairs; warm-up {Wu} steps done")
+    # the whole protocol, timed once
     sim.set_state(w.spin0, -1)
     sim.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    flips = sim.run(0, K)
+    flips_all = sim.run(0, w.n_steps)
+    torch.cuda.synchronize()
+    dt_all = time.perf_counter() - t0
+    tm_all = sim.timing()
+    per_step = sim.step_flips()
+    full = {"steps": w.n_steps, "seconds": dt_all, "flips": flips_all,
+            "neighbour_interactions_per_s": E * w.n_steps / dt_all,
+            "flips_per_s": flips_all / dt_all, "ms_per_step": dt_all / w.n_steps * 1e3,
+            "field_pass_avg_us": tm_all["field_ms"] / max(1, tm_all["field_launches"]) * 1e3,
+            "relax_ms": tm_all["relax_ms"],
+            "relax_ns_per_flip": tm_all["relax_ms"] * 1e6 / max(1, flips_all),
+            "mean_flips_per_step": float(np.mean(per_step)),
+            "max_flips_per_step": int(np.max(per_step))}
+    progress(f"whole protocol: {flips_all} flips in {dt_all:.2f} s")
+    # the timed window, from the state an untimed prefix leaves
+    a = representative_window(per_step, K)
+    sim.set_state(w.spin0, -1)
+    if a > 0:
+        sim.run(0, a)
+    spins_a = sim.state()[0]
+    sim.set_state(spins_a, a - 1)      # the window's own flip log and checksum
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flips = sim.run(a, a + K)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     tm = sim.timing()
+    lg = sim.flip_log(cap=0)
+    # the same window on the one-flip-at-a-time tree only (no speculation)
+    t = sim.tuning()
+    sim.set_tuning(t["relax_waves"], t["l1_shift"], 2 ** 62)
+    sim.set_state(spins_a, a - 1)
+    sim.set_timing(True)
+    sim.run(a, a + K)
+    tm_tree = sim.timing()
+    tree_same = sim.flip_log(cap=0)["hash"] == lg["hash"]
+    sim.close()
     field_avg_s = tm["field_ms"] / max(1, tm["field_launches"]) / 1e3
     achieved = info["field_pass_bytes"] / field_avg_s / 1e9
+    lat = latency_reference(asi)
+    ns_flip = tm["relax_ms"] * 1e6 / max(1, flips)
+    ns_flip_tree = tm_tree["relax_ms"] * 1e6 / max(1, flips)
+    traffic = (recorded_traffic() if w.name == "kagome577_rotating"
+               and args.local_field == "none" else None)
     out = {
         "metric": METRIC,
         "value": E * K / dt,
         "unit": "neighbour interactions/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": W,
+        "warmup": Wu,
         "ms_per_step": dt / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -136,31 +236,51 @@ def bench_plain(args, asi, workloads, torch):
         "config": {"workload": w.name, "magnets": N, "neighbour_pairs": E,
                    "max_degree": info["max_degree"], "neighbor_distance": w.neighbor_distance,
                    "thermal_std": w.thermal_std, "protocol_steps": w.n_steps,
+                   "timed_steps": f"{a}..{a + K - 1}",
                    "field_pass": "full every step", "parallelism": "single instance, one GPU",
                    "local_field": args.local_field},
+        "window": {"first_step": a, "steps": K, "flips": flips,
+                   "mean_flips_per_step": flips / K,
+                   "run_mean_flips_per_step": full["mean_flips_per_step"],
+                   "how": "the K consecutive steps whose mean flips per step is nearest the "
+                          "whole protocol's mean, reached by an untimed prefix"},
         "flips_per_s": flips / dt,
         "flips": flips,
         "field_calcs_per_s": N * K / dt,
+        "full_protocol": full,
         "field_pass": {"avg_us": field_avg_s * 1e6, "launches": tm["field_launches"],
                        "algorithmic_bytes": info["field_pass_bytes"],
                        "neighbour_interactions_per_s": E / field_avg_s,
                        "field_calcs_per_s": N / field_avg_s},
         "relax": {"ms_total": tm["relax_ms"], "launches": tm["relax_launches"],
-                  "ns_per_flip": tm["relax_ms"] * 1e6 / max(1, flips),
-                  "flips_per_s_in_kernel": flips / max(1e-9, tm["relax_ms"] / 1e3)},
+                  "ns_per_flip": ns_flip,
+                  "flips_per_s_in_kernel": flips / max(1e-9, tm["relax_ms"] / 1e3),
+                  "tree_only_ns_per_flip": ns_flip_tree,
+                  "tree_only_flips_equal": bool(tree_same),
+                  "latency_reference_ns": lat,
+                  "ns_per_flip_over_l2_gather": ns_flip / lat["l2_4MiB_lanes64_ns"],
+                  "tree_ns_per_flip_over_l2_gather": ns_flip_tree / lat["l2_4MiB_lanes64_ns"],
+                  "ns_per_flip_over_hbm_load": ns_flip / lat["hbm_1GiB_lanes1_ns"],
+                  "tree_ns_per_flip_over_hbm_load": ns_flip_tree / lat["hbm_1GiB_lanes1_ns"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (recorded_traffic() if w.name == "kagome577_rotating"
-                                 and args.local_field == "none" else None),
+                     "traffic": traffic,
+                     "traffic_source": ({"profile": os.path.relpath(PROFILE, ROOT),
+                                         "field_pass_source_sha256": field_pass_digest(),
+                                         "measured_in_this_run": False,
+                                         "note": "counter bytes per launch from the committed "
+                                                 "rocprofv3 --pmc summary, used only while the "
+                                                 "kernel source digest matches"}
+                                        if traffic is not None else None),
                      "kernel": ("k_field_hd (full-field pass, a workgroup per 64-row slice)"
                                 if info["max_degree"] >= HD_MIN_DEGREE
                                 else "k_field (full-field pass, a lane per row)")},
         "paper_context": {"field_calcs_per_s": 1e8, "hardware": "NVIDIA Tesla V100 32GB",
                           "workload": "square ASI, 8-spin neighbourhood, saturated size"},
     }
-    sim.close()
     if not args.no_cpu_baseline and args.local_field != "wave":
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        progress("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(w, a, K, spins_a, {"flips": flips, "hash": lg["hash"]})
     return out
 
 
@@ -217,7 +337,7 @@ def bench_batched(args, asi, workloads, torch):
     """Uneven sweep of instances: one batched run (one field launch and one
     relax launch per step, replayed from a captured graph) against the same
     instances run one after another with asi_run."""
-    K = 500 if args.steps is None else args.steps
+    K = 500 if args.steps is None or args.mode == "all" else args.steps
     ws = workloads.batched_sweep(count=args.count, seed=4, n_steps=K)
     sims = [asi.Sim.from_workload(w) for w in ws]
     ntot = sum(w.n for w in ws)
@@ -363,13 +483,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--mode", choices=["plain", "batched", "served", "analysis"], default="plain")
+    ap.add_argument("--mode", choices=["all", "plain", "batched", "served", "analysis"],
+                    default="all")
     ap.add_argument("--workload", default="kagome577_rotating")
     ap.add_argument("--local-field", default="none", choices=["none", "gradient", "wave"],
                     help="plain: add a static spatial field, or a travelling wave "
                          "evaluated on the device (no CPU baseline for the wave)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--count", type=int, default=256, help="batched: instances")
     ap.add_argument("--batch-mode", default="fused", choices=["lockstep", "graph", "fused"])
     ap.add_argument("--tune-steps", type=int, default=20,
@@ -393,9 +513,25 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    fn = {"plain": bench_plain, "batched": bench_batched, "served": bench_served,
-          "analysis": bench_analysis}[args.mode]
-    print(json.dumps(fn(args, asi, workloads, torch)), flush=True)
+    if args.mode != "all":
+        fn = {"plain": bench_plain, "batched": bench_batched, "served": bench_served,
+              "analysis": bench_analysis}[args.mode]
+        print(json.dumps(fn(args, asi, workloads, torch)), flush=True)
+        return
+    # the default: the 1M-magnet kagome (value and roofline), then the
+    # batched sweep and the served stream, each against its plain runs
+    t_all = time.perf_counter()
+    out = bench_plain(args, asi, workloads, torch)
+    progress(f"plain done at {time.perf_counter() - t_all:.1f}s")
+    contract = ("metric", "n_gpus", "steps", "warmup", "higher_is_better", "scaling",
+                "vs_baseline", "data")
+    for mode, fn in (("batched", bench_batched), ("served", bench_served)):
+        torch.cuda.empty_cache()     # the previous phase's memory back to the device
+        r = fn(args, asi, workloads, torch)
+        out[mode] = {k: v for k, v in r.items() if k not in contract}
+        progress(f"{mode} done at {time.perf_counter() - t_all:.1f}s")
+    out["bench_seconds"] = time.perf_counter() - t_all
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
