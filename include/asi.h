@@ -204,15 +204,18 @@ asi_status asi_get_magnetization_log(asi_handle h, double* out);
  * flips_out (may be NULL) receives the number of flips of this call. */
 asi_status asi_relax(asi_handle h, int64_t* flips_out);
 
-/* For t = t_begin .. t_end-1: set the fields of step t (applied H[t] and
- * the thermal draw of step t) and relax.  Requires 0 <= t_begin <= t_end <=
+/* The time loop of Sec. II.H: for t = t_begin .. t_end-1, set the fields of
+ * step t (applied H[t] of Sec. II.D and the thermal draw of Sec. II.E, both
+ * held fixed while the step relaxes) and relax to stability.  Requires 0 <= t_begin <= t_end <=
  * n_steps.  flips_out (may be NULL): flips of this call.  Stops early with
  * ASI_ELOOP when one step exceeds max_flips_per_step. */
 asi_status asi_run(asi_handle h, int64_t t_begin, int64_t t_end, int64_t* flips_out);
 
-/* Current state: spins [n], total fields projected on the easy axis h_par
- * [n] and hard axis h_perp [n] as of the end of the last relax, and the
- * last completed step (-1 if none).  Any pointer may be NULL. */
+/* Current state: spins s_i of Eq. 1 [n], the total field of Eq. 2
+ * projected on the easy axis h_par [n] and hard axis h_perp [n] (the two
+ * components the astroid of Eq. 5 reads, Sec. II.F) as of the end of the
+ * last relax, and the last completed step (-1 if none).  Any pointer may be
+ * NULL. */
 asi_status asi_get_state(asi_handle h, int8_t* spins, double* h_par, double* h_perp,
                          int64_t* step_out);
 
@@ -224,8 +227,9 @@ asi_status asi_get_state(asi_handle h, int8_t* spins, double* h_par, double* h_p
  * re-gathered ones by rounding only.  Resets the flip log and its hash. */
 asi_status asi_set_state(asi_handle h, const int8_t* spins, int64_t step);
 
-/* Flip log: the first min(count, cap, flip_log_capacity) flips as
- * (step, magnet index), the
+/* Flip log of the relax of Sec. II.H, one entry per switching event of
+ * Sec. II.F in the order the relax performed them: the first
+ * min(count, cap, flip_log_capacity) flips as (step, magnet index), the
  * total number of flips logged since create / set_state, and a running hash
  * over all of them: hash = 0xcbf29ce484222325, then for each flip
  * hash = (hash ^ ((uint64)(uint32)step << 32 | (uint32)index)) * 0x100000001b3
