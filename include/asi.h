@@ -191,6 +191,21 @@ asi_status asi_switching_order(asi_handle h, int64_t* pos_out);
  * different n or n outside 2 .. 2^27; ASI_ESTATE as asi_switching_order. */
 asi_status asi_switching_rho(asi_handle a, asi_handle b, double* rho_out, int64_t* sums_out);
 
+/* asi_switching_rho for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same rho and sums, bit for bit, with no hipMalloc, hipFree
+ * or allocator callback.  Its working memory is one static device array per
+ * GPU (about 33 MB, held until the process ends), found with
+ * hipGetSymbolAddress on the first call on each GPU.  Limits: n in 2 .. 2^20
+ * and at most 2^24 flips in each instance's log, else ASI_EINVAL; both
+ * handles on the same GPU.  Every call on a GPU shares that GPU's array:
+ * calls are serialised within the process by a lock and each synchronises
+ * before returning, and no call depends on what an earlier one left there;
+ * a call that overlapped another on the same array (another copy of the
+ * library in the same process) would race.  Errors as asi_switching_rho. */
+asi_status asi_switching_rho_noalloc(asi_handle a, asi_handle b, double* rho_out,
+                                     int64_t* sums_out);
+
 /* Per-step magnetisation log: while enabled, asi_run and asi_relax record M
  * after the relax of every step t they run into row t of a device array of
  * the protocol's length (rows of steps not run hold NaN; a new protocol

@@ -98,6 +98,7 @@ SIGNATURES = {
     "asi_group_magnetization": [P, C.c_int64, P, P, P],
     "asi_switching_order": [P, P],
     "asi_switching_rho": [P, P, C.POINTER(C.c_double), P],
+    "asi_switching_rho_noalloc": [P, P, C.POINTER(C.c_double), P],
     "asi_set_magnetization_log": [P, C.c_int32],
     "asi_get_magnetization_log": [P, P],
     "asi_relax": [P, I64P],
@@ -462,6 +463,16 @@ def switching_rho(a: Sim, b: Sim):
     rho = C.c_double(0.0)
     sums = np.zeros(6, dtype=np.int64)
     _check(library().asi_switching_rho(a.handle, b.handle, C.byref(rho), _ptr(sums)))
+    tot = tuple(int(np.uint64(sums[2 * c])) + (int(sums[2 * c + 1]) << 64) for c in range(3))
+    return rho.value, tot
+
+
+def switching_rho_noalloc(a: Sim, b: Sim):
+    """switching_rho through the allocation-free entry point (static device
+    scratch; n <= 2^20, logs <= 2^24 flips)."""
+    rho = C.c_double(0.0)
+    sums = np.zeros(6, dtype=np.int64)
+    _check(library().asi_switching_rho_noalloc(a.handle, b.handle, C.byref(rho), _ptr(sums)))
     tot = tuple(int(np.uint64(sums[2 * c])) + (int(sums[2 * c + 1]) << 64) for c in range(3))
     return rho.value, tot
 

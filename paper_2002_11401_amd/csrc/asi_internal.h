@@ -143,6 +143,27 @@ constexpr int64_t kRankCorrMaxN = (int64_t)1 << 27;
 int64_t rank_corr_blocks(int64_t n);
 void launch_rank_correlation(const int64_t* r2a, const int64_t* r2b, int64_t n, long long* part,
                              hipStream_t st);
+// Exact totals of the rank_correlation block sums (Sab, Saa, Sbb) into
+// tot[6] as 128-bit two's complement (low, high) pairs; one workgroup.
+void launch_rank_corr_total(const long long* part, int64_t nb, long long* tot, hipStream_t st);
+// Allocation-free comparison of switching orders: size limits and the
+// regions of the library's static device scratch (one copy per GPU, held
+// until the process ends), carved from its device address.
+constexpr int64_t kStaticRhoMaxN = (int64_t)1 << 20;    // magnets per instance
+constexpr int64_t kStaticRhoMaxLog = (int64_t)1 << 24;  // flips in each flip log
+struct StaticRhoScratch {
+  unsigned long long* pos[2];  // [kStaticRhoMaxN] first-switch positions of a, b
+  int64_t* r2[2];              // [kStaticRhoMaxN] twice-average ranks of a, b
+  int64_t* tmp[2];             // [switching_scratch_count(kStaticRhoMaxLog)] of a, b
+  long long* part;             // [3 rank_corr_blocks(kStaticRhoMaxN)]
+  long long* tot;              // [6]
+};
+size_t static_scratch_bytes();
+StaticRhoScratch carve_static_rho(unsigned char* base);
+// Device address of the static scratch on the current device: looked up
+// with hipGetSymbolAddress on the first call on each device (with that
+// device current), then taken from a per-device table.
+hipError_t static_scratch_address(unsigned char** out);
 // Pointer chase (measurement): lanes 0 .. lanes-1 (<= 64) of one wavefront
 // each take `hops` dependent loads along chain from starts[lane]; out[0] =
 // elapsed device-clock ticks, out[1 + lane] = each lane's last index.

@@ -20,6 +20,7 @@
 //                           (field phase + relax) through its own protocol
 #include <algorithm>
 #include <climits>
+#include <mutex>
 
 #include "asi_internal.h"
 
@@ -2223,6 +2224,49 @@ k_rank_corr(const int64_t* __restrict__ r2a, const int64_t* __restrict__ r2b, in
   }
 }
 
+// Exact totals of the nb block sums of k_rank_corr, one workgroup: each
+// thread adds a strided subset of the blocks into 128-bit (low, high)
+// accumulators, then the threads' accumulators are added pairwise in LDS.
+// Integer sums, so the totals do not depend on the order (|total| < 2^81).
+struct I128 {
+  unsigned long long lo;
+  long long hi;
+};
+
+__device__ inline I128 add128(I128 a, I128 b) {
+  I128 r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo ? 1 : 0);
+  return r;
+}
+
+__device__ inline I128 widen(long long v) {
+  I128 r;
+  r.lo = (unsigned long long)v;
+  r.hi = v < 0 ? -1 : 0;
+  return r;
+}
+
+__global__ void __launch_bounds__(kCorrRankThreads)
+k_rank_corr_total(const long long* __restrict__ part, int64_t nb, long long* __restrict__ tot) {
+  __shared__ I128 acc[3][kCorrRankThreads];
+  const int tid = threadIdx.x;
+  I128 a[3] = {{0ull, 0}, {0ull, 0}, {0ull, 0}};
+  for (int64_t b = tid; b < nb; b += kCorrRankThreads)
+    for (int c = 0; c < 3; ++c) a[c] = add128(a[c], widen(part[3 * b + c]));
+  for (int c = 0; c < 3; ++c) acc[c][tid] = a[c];
+  __syncthreads();
+  for (int w = kCorrRankThreads / 2; w > 0; w >>= 1) {
+    if (tid < w)
+      for (int c = 0; c < 3; ++c) acc[c][tid] = add128(acc[c][tid], acc[c][tid + w]);
+    __syncthreads();
+  }
+  if (tid < 3) {
+    tot[2 * tid] = (long long)acc[tid][0].lo;
+    tot[2 * tid + 1] = acc[tid][0].hi;
+  }
+}
+
 // ------------------------------------------------------------ measurement
 // Dependent-load latency: each of the first `lanes` lanes of one wavefront
 // follows a chain of indices from its own start (each load's address comes
@@ -2276,6 +2320,70 @@ void launch_switching_ranks(const int32_t* log_j, int64_t L, int64_t n, unsigned
 }
 
 int64_t rank_corr_blocks(int64_t n) { return (n + kCorrRankThreads - 1) / kCorrRankThreads; }
+
+void launch_rank_corr_total(const long long* part, int64_t nb, long long* tot, hipStream_t st) {
+  hipLaunchKernelGGL(k_rank_corr_total, dim3(1), dim3(kCorrRankThreads), 0, st, part, nb, tot);
+}
+
+// ------------------------------------------------------------ static scratch
+// Scratch of the allocation-free switching-order comparison: one array per
+// GPU for the life of the process.  In host code `scratch` only names the
+// symbol; its device address comes from hipGetSymbolAddress, per device.
+namespace {
+
+constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+constexpr size_t kRhoRankBytes = align256(8 * (size_t)kStaticRhoMaxN);
+constexpr size_t kRhoTmpBytes =
+    align256(8 * (size_t)(2 * ((kStaticRhoMaxLog + kRankBlock - 1) / kRankBlock) + 1));
+constexpr size_t kRhoPartBytes =
+    align256(8 * 3 * (size_t)((kStaticRhoMaxN + kCorrRankThreads - 1) / kCorrRankThreads));
+constexpr size_t kRhoTotBytes = align256(8 * 6);
+constexpr size_t kScratchBytes = 4 * kRhoRankBytes + 2 * kRhoTmpBytes + kRhoPartBytes + kRhoTotBytes;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxScratchDevices] = {};
+
+}  // namespace
+
+size_t static_scratch_bytes() { return kScratchBytes; }
+
+StaticRhoScratch carve_static_rho(unsigned char* base) {
+  StaticRhoScratch S;
+  size_t off = 0;
+  for (int k = 0; k < 2; ++k) {
+    S.pos[k] = reinterpret_cast<unsigned long long*>(base + off);
+    off += kRhoRankBytes;
+    S.r2[k] = reinterpret_cast<int64_t*>(base + off);
+    off += kRhoRankBytes;
+  }
+  for (int k = 0; k < 2; ++k) {
+    S.tmp[k] = reinterpret_cast<int64_t*>(base + off);
+    off += kRhoTmpBytes;
+  }
+  S.part = reinterpret_cast<long long*>(base + off);
+  off += kRhoPartBytes;
+  S.tot = reinterpret_cast<long long*>(base + off);
+  return S;
+}
+
+hipError_t static_scratch_address(unsigned char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 void launch_rank_correlation(const int64_t* r2a, const int64_t* r2b, int64_t n, long long* part,
                              hipStream_t st) {

@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/asi.h"
@@ -93,6 +94,7 @@ struct TimerPair {
 struct asi_sim {
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  int device = 0;              // current device at create: the handle's GPU
   DevMem mem;
   int64_t n = 0, E = 0;
   int32_t D = 0, l1s = 6, relax_waves = 1;
@@ -270,6 +272,7 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
       return fail(ASI_EDEVICE, std::string("kernel configuration: ") + hipGetErrorString(cfg));
   }
   if (dev) s->mem.dev = *dev;
+  HIPCHK(hipGetDevice(&s->device), s);
   if (dev && dev->stream) {
     s->stream = (hipStream_t)dev->stream;
   } else {
@@ -879,6 +882,79 @@ asi_status asi_switching_rho(asi_handle a, asi_handle b, double* rho_out, int64_
       sums_out[2 * c] = (int64_t)(uint64_t)sum[c];                  // low 64 bits
       sums_out[2 * c + 1] = (int64_t)(uint64_t)(sum[c] >> 64);      // high 64 bits (signed)
     }
+  return ASI_OK;
+}
+
+asi_status asi_switching_rho_noalloc(asi_handle a, asi_handle b, double* rho_out,
+                                     int64_t* sums_out) {
+  asi_status st = check_handle(a);
+  if (st == ASI_OK) st = check_handle(b);
+  if (st != ASI_OK) return st;
+  if (!rho_out) return fail(ASI_EINVAL, "rho_out is NULL");
+  if (a->n != b->n) return fail(ASI_EINVAL, "the two instances differ in size");
+  if (a->device != b->device) return fail(ASI_EINVAL, "the two instances are on different GPUs");
+  if (a->n < 2 || a->n > kStaticRhoMaxN)
+    return fail(ASI_EINVAL, "n must be in 2 .. 2^20 for the allocation-free comparison (n = " +
+                                std::to_string(a->n) + "); asi_switching_rho takes up to 2^27");
+  const int64_t n = a->n;
+  RunDev ra{}, rb{};
+  st = read_run(a, &ra);
+  if (st == ASI_OK) st = read_run(b, &rb);
+  if (st != ASI_OK) return st;
+  for (const auto& r : {std::make_pair(a, ra.flips), std::make_pair(b, rb.flips)}) {
+    if (r.second > r.first->hI.log_cap)
+      return fail(ASI_ESTATE, "the flip log holds " + std::to_string(r.first->hI.log_cap) +
+                                  " of " + std::to_string(r.second) +
+                                  " flips: raise flip_log_capacity to compare switching orders");
+    if (r.second > kStaticRhoMaxLog)
+      return fail(ASI_EINVAL, "a flip log of " + std::to_string(r.second) +
+                                  " flips exceeds the allocation-free limit of 2^24");
+  }
+  // the handles' GPU current while its scratch is looked up and used
+  int prev = 0;
+  HIPCHK(hipGetDevice(&prev), a);
+  if (prev != a->device) HIPCHK(hipSetDevice(a->device), a);
+  struct Restore {
+    int dev, prev;
+    ~Restore() {
+      if (dev != prev) (void)hipSetDevice(prev);
+    }
+  } restore{a->device, prev};
+  unsigned char* base = nullptr;
+  HIPCHK(static_scratch_address(&base), a);
+  const StaticRhoScratch S = carve_static_rho(base);
+  // one call at a time per process: every call on a GPU uses its one array
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  // every scratch word this call reads is written earlier in the call, so
+  // nothing needs clearing between calls
+  launch_switching_ranks(a->hI.log_j, ra.flips, n, S.pos[0], S.r2[0], S.tmp[0], a->stream);
+  HIPCHK(hipGetLastError(), a);
+  const int64_t* r2b = S.r2[0];
+  if (b != a) {
+    launch_switching_ranks(b->hI.log_j, rb.flips, n, S.pos[1], S.r2[1], S.tmp[1], b->stream);
+    HIPCHK(hipGetLastError(), b);
+    st = sync_and_check(b);  // b's ranks are read on a's stream
+    if (st != ASI_OK) return st;
+    r2b = S.r2[1];
+  }
+  const int64_t nb = rank_corr_blocks(n);
+  launch_rank_correlation(S.r2[0], r2b, n, S.part, a->stream);
+  launch_rank_corr_total(S.part, nb, S.tot, a->stream);
+  HIPCHK(hipGetLastError(), a);
+  int64_t tot[6];
+  HIPCHK(hipMemcpyAsync(tot, S.tot, sizeof(tot), hipMemcpyDeviceToHost, a->stream), a);
+  st = sync_and_check(a);
+  if (st != ASI_OK) return st;
+  __int128 sum[3];
+  for (int c = 0; c < 3; ++c)
+    sum[c] = (__int128)(((unsigned __int128)(uint64_t)tot[2 * c + 1] << 64) |
+                        (unsigned __int128)(uint64_t)tot[2 * c]);
+  const double sab = (double)sum[0], saa = (double)sum[1], sbb = (double)sum[2];
+  const double den = std::sqrt(saa * sbb);
+  *rho_out = den > 0.0 ? sab / den : std::nan("");
+  if (sums_out)
+    for (int c = 0; c < 6; ++c) sums_out[c] = tot[c];
   return ASI_OK;
 }
 
