@@ -506,71 +506,101 @@ __global__ __launch_bounds__(kFieldBlock) void k_field(const InstDev* __restrict
   if (bal) pool_put(I, key, payload, bal, (int64_t)bbase + wcount[wave]);
 }
 
-// Full-field pass for an instance of high degree (every row gathered): one
-// workgroup of kHdThreads per 64-row slice.  The slice's tables are one
-// contiguous block (slot k of its rows at k * 64 + lane); the workgroup
-// reads them in chunks of kHdChunk slots, four entries per thread with the
-// next chunk's columns prefetched, so a chunk costs one round trip for the
-// whole block instead of one per eight slots per row, and stages each slot's
-// signed couplings in LDS.  The lane of each row then adds its chunk in
-// ascending slot order: the same sums, in the same order, as field_row.
+// Full-field pass for an instance of high degree (every row gathered): a
+// workgroup of 8 R threads takes R consecutive rows of a 64-row slice (R =
+// 64, 32, 16 or 8, fewer rows per workgroup for smaller instances, so that
+// the device holds enough workgroups).  Each thread keeps one row, so it
+// loads only that row's real slots (slot < len): no padding is read.  The
+// slots are read in chunks of kHdChunk, eight entries per thread, the next
+// chunk's couplings and spins in flight while the current one is added and
+// the columns two chunks ahead; each entry's signed couplings are staged in
+// LDS, and the lane of each row adds its chunk in ascending slot order: the
+// same sums, in the same order, as field_row.  The workgroups of one slice
+// are launched on the same XCD (block ids that differ by multiples of 8),
+// so lines shared by two of them are fetched into one L2.
 constexpr int kHdChunk = 64;
-constexpr int kHdThreads = 512;
-constexpr int kHdPer = kHdChunk * 64 / kHdThreads;  // entries per thread per chunk
+constexpr int kHdPer = 8;  // entries per thread per chunk
 
-__global__ __launch_bounds__(kHdThreads) void k_field_hd(const InstDev* __restrict__ insts,
-                                                   RunDev* __restrict__ runs) {
-  __shared__ double sa[kHdChunk * 64];
-  __shared__ double sb[kHdChunk * 64];
-  const RunDev* R = runs;
-  if (!R->active) return;
+template <int R>
+__global__ __launch_bounds__(8 * R) void k_field_hd(const InstDev* __restrict__ insts,
+                                                    RunDev* __restrict__ runs) {
+  constexpr int S = 64 / R;  // workgroups per slice
+  __shared__ double sa[kHdChunk * R];
+  __shared__ double sb[kHdChunk * R];
+  __shared__ int lmax;
+  const RunDev* Rn = runs;
+  if (!Rn->active) return;
   const InstDev* I = insts;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int q = blockIdx.x;
+  const int64_t slice = (int64_t)(q / (8 * S)) * 8 + (q % 8);
+  const int sub = (q / 8) % S;
+  const int64_t row0 = slice * 64;
+  if (row0 >= I->n) return;
+  const int tid = threadIdx.x;
+  const int r = tid % R;    // the thread's row in the workgroup's R rows
+  const int s0 = tid / R;   // its first slot in a chunk; then every 8th
+  const int64_t i = row0 + sub * R + r;
+  const int32_t L = (i < I->n) ? I->len[i] : 0;
   const int32_t D = I->D;
-  const int64_t base = slot_of(row0, D, 0);  // start of the slice's block
+  const int64_t base = slot_of(row0, D, 0) + sub * R + r;  // slot 0 of the thread's row
   const int8_t* __restrict__ s = I->s;
-  const int64_t i = row0 + lane;
-  const bool own = tid < 64 && i < I->n;   // wavefront 0 owns the rows
-  const int32_t L = own ? I->len[i] : 0;
+  if (tid == 0) lmax = 0;
+  __syncthreads();
+  if (tid < R && L > 0) atomicMax(&lmax, L);
+  __syncthreads();
+  const int32_t Lw = lmax;  // slots of the longest of the workgroup's rows
   double p = 0.0, pq = 0.0;
   int32_t jc[kHdPer];
+  double a[kHdPer], b[kHdPer];
+  int sg[kHdPer];
+  // chunk 0: columns, then couplings and spins; columns of chunk 1
 #pragma unroll
-  for (int q = 0; q < kHdPer; ++q) {
-    const int e = tid + q * kHdThreads;
-    jc[q] = (e / 64 < D) ? __builtin_nontemporal_load(&I->col[base + e]) : -1;
+  for (int u = 0; u < kHdPer; ++u) {
+    const int k = s0 + 8 * u;
+    jc[u] = (k < L) ? __builtin_nontemporal_load(&I->col[base + (int64_t)k * 64]) : 0;
   }
-  for (int32_t k0 = 0; k0 < D; k0 += kHdChunk) {
-    double a[kHdPer], b[kHdPer];
-    int sg[kHdPer];
 #pragma unroll
-    for (int q = 0; q < kHdPer; ++q) {
-      const int e = tid + q * kHdThreads;
-      const bool ok = k0 + e / 64 < D;
-      const int64_t sl = base + (int64_t)k0 * 64 + e;
-      a[q] = ok ? __builtin_nontemporal_load(&I->A[sl]) : 0.0;
-      b[q] = ok ? __builtin_nontemporal_load(&I->B[sl]) : 0.0;
-      sg[q] = (ok && jc[q] >= 0) ? s[jc[q]] : 0;
-    }
+  for (int u = 0; u < kHdPer; ++u) {
+    const int k = s0 + 8 * u;
+    const bool ok = k < L;
+    a[u] = ok ? __builtin_nontemporal_load(&I->A[base + (int64_t)k * 64]) : 0.0;
+    b[u] = ok ? __builtin_nontemporal_load(&I->B[base + (int64_t)k * 64]) : 0.0;
+    sg[u] = ok ? s[jc[u]] : 0;
+  }
 #pragma unroll
-    for (int q = 0; q < kHdPer; ++q) {
-      const int e = tid + q * kHdThreads;
-      const bool ok = k0 + kHdChunk + e / 64 < D;
-      jc[q] = ok ? __builtin_nontemporal_load(&I->col[base + (int64_t)(k0 + kHdChunk) * 64 + e])
-                 : -1;
-    }
+  for (int u = 0; u < kHdPer; ++u) {
+    const int k = kHdChunk + s0 + 8 * u;
+    jc[u] = (k < L) ? __builtin_nontemporal_load(&I->col[base + (int64_t)k * 64]) : 0;
+  }
+  for (int32_t k0 = 0; k0 < Lw; k0 += kHdChunk) {
 #pragma unroll
-    for (int q = 0; q < kHdPer; ++q) {
-      const int e = tid + q * kHdThreads;
-      sa[e] = (sg[q] > 0) ? a[q] : -a[q];
-      sb[e] = (sg[q] > 0) ? b[q] : -b[q];
+    for (int u = 0; u < kHdPer; ++u) {
+      const int e = (s0 + 8 * u) * R + r;
+      sa[e] = (sg[u] > 0) ? a[u] : -a[u];
+      sb[e] = (sg[u] > 0) ? b[u] : -b[u];
     }
     __syncthreads();
-    if (own) {
+    // the next chunk's couplings and spins, and the columns after it, are
+    // loaded while the current chunk is added
+    const int32_t k1 = k0 + kHdChunk;
+#pragma unroll
+    for (int u = 0; u < kHdPer; ++u) {
+      const int k = k1 + s0 + 8 * u;
+      const bool ok = k < L;
+      a[u] = ok ? __builtin_nontemporal_load(&I->A[base + (int64_t)k * 64]) : 0.0;
+      b[u] = ok ? __builtin_nontemporal_load(&I->B[base + (int64_t)k * 64]) : 0.0;
+      sg[u] = ok ? s[jc[u]] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kHdPer; ++u) {
+      const int k = k1 + kHdChunk + s0 + 8 * u;
+      jc[u] = (k < L) ? __builtin_nontemporal_load(&I->col[base + (int64_t)k * 64]) : 0;
+    }
+    if (tid < R) {
       const int kn = L - k0 < kHdChunk ? L - k0 : kHdChunk;
       for (int kk = 0; kk < kn; ++kk) {
-        p += sa[kk * 64 + lane];
-        pq += sb[kk * 64 + lane];
+        p += sa[kk * R + tid];
+        pq += sb[kk * R + tid];
       }
     }
     __syncthreads();
@@ -578,20 +608,45 @@ __global__ __launch_bounds__(kHdThreads) void k_field_hd(const InstDev* __restri
   if (tid >= 64) return;
   uint32_t payload = 0;
   double key = 0.0;
-  if (own) key = field_finish(I, i, R->t, p, pq, payload);
-  double mk = key;
-  uint32_t mp = payload;
-  wave_argmax(mk, mp);
-  if (lane == 0) {
-    I->t1key[row0 >> 6] = mk;
-    I->t1idx[row0 >> 6] = mp;
+  if (tid < R && i < I->n) key = field_finish(I, i, Rn->t, p, pq, payload);
+  if (S == 1) {
+    double mk = key;
+    uint32_t mp = payload;
+    wave_argmax(mk, mp);
+    if (tid == 0) {
+      I->t1key[row0 >> 6] = mk;
+      I->t1idx[row0 >> 6] = mp;
+    }
   }
   const unsigned long long bal = __ballot(key > 0.0);
   if (bal) {
     int pbase = 0;
-    if (lane == 0) pbase = atomicAdd(I->ccount, __popcll(bal));
+    if (tid == 0) pbase = atomicAdd(I->ccount, __popcll(bal));
     pbase = __builtin_amdgcn_readfirstlane(pbase);
     pool_put(I, key, payload, bal, pbase);
+  }
+}
+
+// Per-64-row maxima of the keys a split high-degree pass wrote (one
+// wavefront per 64 rows), for the relax tree.
+__global__ __launch_bounds__(256) void k_slice_max(const InstDev* __restrict__ insts,
+                                                   RunDev* __restrict__ runs) {
+  if (!runs->active) return;
+  const InstDev* I = insts;
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t i = (g << 6) + lane;
+  if ((g << 6) >= I->n) return;
+  double k = 0.0;
+  uint32_t pay = 0u;
+  if (i < I->n) {
+    k = I->key[i];
+    pay = (uint32_t)i | (I->s[i] < 0 ? 0x80000000u : 0u);
+  }
+  wave_argmax(k, pay);
+  if (lane == 0) {
+    I->t1key[g] = k;
+    I->t1idx[g] = pay;
   }
 }
 
@@ -2453,9 +2508,27 @@ void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,
 }
 
 void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, hipStream_t st) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_field_hd, dim3((unsigned)((n + 63) / 64)), dim3(kHdThreads), 0, st, inst,
-                     run);
+  // rows per workgroup: the largest that still gives the device about four
+  // workgroups per compute unit, at least 8
+  const int64_t nsl = (n + 63) / 64;
+  const int R = nsl >= 1024 ? 64 : 2 * nsl >= 1024 ? 32 : 4 * nsl >= 1024 ? 16 : 8;
+  const unsigned blocks = (unsigned)(((nsl + 7) / 8) * 8 * (64 / R));
+  switch (R) {
+    case 64:
+      hipLaunchKernelGGL(k_field_hd<64>, dim3(blocks), dim3(512), 0, st, inst, run);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_field_hd<32>, dim3(blocks), dim3(256), 0, st, inst, run);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_field_hd<16>, dim3(blocks), dim3(128), 0, st, inst, run);
+      break;
+    default:
+      hipLaunchKernelGGL(k_field_hd<8>, dim3(blocks), dim3(64), 0, st, inst, run);
+      break;
+  }
+  if (R < 64)
+    hipLaunchKernelGGL(k_slice_max, dim3((unsigned)((nsl + 3) / 4)), dim3(256), 0, st, inst, run);
 }
 
 void launch_relax(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,

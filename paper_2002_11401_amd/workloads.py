@@ -342,6 +342,19 @@ def pinwheel_100x100_reversal(n_steps: int = 2000) -> Workload:
                     beta=1.5, gamma=3.9)
 
 
+def pinwheel_300x300_reversal(n_steps: int = 2000) -> Workload:
+    """180,600-magnet pinwheel at d = 10 (the 100 x 100 reversal's physics on
+    a 300 x 300 array): ~105 M neighbour pairs, 2.1 GB of tables per
+    full-field pass, far past the 256 MB last-level cache."""
+    xy, theta = pinwheel_diamond(300)
+    H = linear_ramp(2000, 0.1, -0.1, 30.0)[:n_steps]
+    return Workload("pinwheel300_reversal", xy, theta,
+                    polarised_spins(theta, H[0]),
+                    disorder_hk(len(theta), 0.2, 0.05, 1), np.ascontiguousarray(H),
+                    alpha=0.0013, neighbor_distance=10.0, b=0.38, c=1.0,
+                    beta=1.5, gamma=3.9)
+
+
 def kagome_1m_rotating(n_steps: int = 2000, cells: int = 577) -> Workload:
     """~1.0M-magnet kagome (577x577 cells), d=3, thermal std 0.005,
     rotating field of 0.08 with 1000 steps per revolution."""
@@ -371,6 +384,7 @@ def square_anneal(side: int = 50, n_steps: int = 200, alpha: float = 0.0015) -> 
 NAMED = {
     "square10_triangle": square_10x10_triangle,
     "pinwheel100_reversal": pinwheel_100x100_reversal,
+    "pinwheel300_reversal": pinwheel_300x300_reversal,
     "kagome577_rotating": kagome_1m_rotating,
     "square50_anneal": square_anneal,
 }

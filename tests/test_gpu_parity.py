@@ -976,12 +976,14 @@ def test_full_pass_and_dirty_row_modes_bitwise():  # noqa: D103
     assert_same_flips(lb, r, b.state()[0], o.spins())
 
 
-@pytest.mark.parametrize("side,d", [(40, 10.0), (23, 7.0)])
+@pytest.mark.parametrize("side,d", [(40, 10.0), (23, 7.0), (97, 7.0), (130, 5.0), (185, 5.0)])
 def test_high_degree_full_pass_bitwise(side, d):
-    """At 128 or more neighbours the full-field pass runs one workgroup per
-    64-row slice; its sums must equal the one-lane-per-row gather bit for bit
-    (dirty mode gathers every row at the first step and the rows next to
-    flips later), and the flips must match the oracle."""
+    """At 128 or more neighbours the full-field pass runs a workgroup per 8,
+    16, 32 or 64 rows of a 64-row slice (by instance size: 3,280 and 1,104
+    magnets take 8 rows, 19,012 take 16, 34,060 take 32, 68,820 take 64; all
+    end in a ragged slice); its sums must equal the one-lane-per-row gather
+    bit for bit (dirty mode gathers every row at the first step and the rows
+    next to flips later), and the flips must match the oracle."""
     xy, theta = W.pinwheel_diamond(side)
     n = len(theta)
     H = W.linear_ramp(80, 0.1, -0.1, 30.0)
