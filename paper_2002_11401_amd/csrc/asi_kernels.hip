@@ -82,8 +82,9 @@ __device__ inline float pow_bound(double x, double e) {
 // Switching key: the left-hand side of Eq. 5 when magnet i may flip, i.e.
 // the field opposes the moment (Eq. 6, s_i h_par < 0) and Eq. 5 exceeds 1;
 // otherwise 0.  Exponents ep = 2/gamma, eq = 2/beta.  When the bound puts
-// the left-hand side below 0.99 the FP64 powers (which could only give a
-// value <= 1) are skipped: the key is the same, bit for bit.
+// the left-hand side below 1 the FP64 powers (which could only give a
+// value <= 1: the bound exceeds their sum) are skipped: the key is the
+// same, bit for bit.
 // In two stages: key_needs_powers settles the key at 0, or gives the
 // normalised field components a and q whose powers decide it.
 __device__ inline bool key_needs_powers(int s, double hp, double hq, double hk, double b,
@@ -92,7 +93,7 @@ __device__ inline bool key_needs_powers(int s, double hp, double hq, double hk, 
   if (!against) return false;
   a = fabs(hp) / (b * hk);
   q = fabs(hq) / (c * hk);
-  return !(pow_bound(a, ep) + pow_bound(q, eq) < 0.99f);
+  return !(pow_bound(a, ep) + pow_bound(q, eq) < 1.0f);
 }
 __device__ inline double key_from_powers(double a, double q, double ep, double eq) {
   const double L = pow(a, ep) + pow(q, eq);
@@ -1618,6 +1619,21 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
 
   while (true) {
     if (wave == 0) {
+      // second level of the groups the last flip touched (one wavefront:
+      // few groups per flip), then the root
+      const int n2 = sh.n2;
+      for (int u = 0; u < n2; ++u) {
+        const int g = L.l2list[u];
+        const int e = g * kL2Group + lane;
+        double k = (e < nt1) ? L.l1k[e] : 0.0;
+        uint32_t p2 = (e < nt1) ? L.l1i[e] : 0u;
+        wave_argmax(k, p2);
+        if (lane == 0) {
+          L.l2k[g] = k;
+          L.l2i[g] = p2;
+          L.l2flag[g] = 0;
+        }
+      }
       double bk = 0.0;
       uint32_t bp = 0;
       for (int u = 0; u < per2; ++u) {
@@ -1635,6 +1651,7 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
         sh.key = bk;
         sh.pay = bp;
         sh.pause = (flips > flips0 && ((flips - flips0) & 15) == 0 && past(deadline)) ? 1 : 0;
+        sh.n2 = 0;
       }
     }
     __syncthreads();
@@ -1652,12 +1669,6 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
     const int64_t j = pay & 0x7fffffffu;
     const int s_new = (pay & 0x80000000u) ? 1 : -1;
     if (tid == 0) {
-      sp[j] = (int8_t)s_new;
-      keyp[j] = 0.0;
-      if (logpos < I->log_cap) {
-        I->log_t[logpos] = (int32_t)t;
-        I->log_j[logpos] = (int32_t)j;
-      }
       const uint64_t w = ((uint64_t)(uint32_t)t << 32) | (uint64_t)(uint32_t)j;
       hash = (hash ^ w) * 0x100000001b3ull;
       const int e = (int)(j >> l1s);
@@ -1715,6 +1726,16 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
           u_s[h] = si;
           u_k[h] = kk;
         }
+      }
+    }
+    // the flipped magnet's own stores, issued after the neighbour loads so
+    // that waiting for those loads does not wait for these
+    if (tid == 0) {
+      sp[j] = (int8_t)s_new;
+      keyp[j] = 0.0;
+      if (logpos - 1 < I->log_cap) {
+        I->log_t[logpos - 1] = (int32_t)t;
+        I->log_j[logpos - 1] = (int32_t)j;
       }
     }
     wave_argmax(tb_k, tb_i);
@@ -1827,21 +1848,6 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
       sh.n1 = 0;
       sh.nr = 0;
     }
-    const int n2 = sh.n2;
-    for (int u = wave; u < n2; u += NW) {
-      const int g = L.l2list[u];
-      const int e = g * kL2Group + lane;
-      double k = (e < nt1) ? L.l1k[e] : 0.0;
-      uint32_t p2 = (e < nt1) ? L.l1i[e] : 0u;
-      wave_argmax(k, p2);
-      if (lane == 0) {
-        L.l2k[g] = k;
-        L.l2i[g] = p2;
-        L.l2flag[g] = 0;
-      }
-    }
-    __syncthreads();
-    if (tid == 0) sh.n2 = 0;
   }
   return status;
 }
