@@ -24,7 +24,8 @@ def hipcc_command(out: str):
     return [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
             "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include"),
-            *SRC, "-o", out]
+            *SRC, "-L", os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib"),
+            "-lrocprofiler-sdk-roctx", "-o", out]
 
 
 def build(verbose: bool = False) -> str:

@@ -17,6 +17,8 @@
 #include "../../include/asi.h"
 #include "asi_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 using namespace asi;
 
 namespace {
@@ -132,6 +134,15 @@ namespace {
       return fail(ASI_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
     }                                                                                  \
   } while (0)
+
+// A named range on the profiler's timeline (roctx) for the duration of a
+// library call: create, run/relax, tune, batch and server bursts.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 hipEvent_t take_event(asi_sim* s) {
   if (!s->spare_events.empty()) {
@@ -553,6 +564,7 @@ extern "C" {
 const char* asi_last_error(void) { return g_err.c_str(); }
 
 asi_status asi_create(const asi_params* params, const asi_device* dev, asi_handle* out) {
+  Range range("asi_create");
   if (!out) return fail(ASI_EINVAL, "out is NULL");
   *out = nullptr;
   auto* s = new (std::nothrow) asi_sim();
@@ -985,12 +997,14 @@ asi_status asi_get_magnetization_log(asi_handle h, double* out) {
 }
 
 asi_status asi_relax(asi_handle h, int64_t* flips_out) {
+  Range range("asi_relax");
   asi_status st = check_handle(h);
   if (st != ASI_OK) return st;
   return run_steps(h, h->cur_step, h->cur_step + 1, flips_out);
 }
 
 asi_status asi_run(asi_handle h, int64_t t_begin, int64_t t_end, int64_t* flips_out) {
+  Range range("asi_run");
   asi_status st = check_handle(h);
   if (st != ASI_OK) return st;
   if (t_begin < 0 || t_begin > t_end || t_end > h->K)
@@ -1037,6 +1051,7 @@ asi_status asi_set_tuning(asi_handle h, const asi_tuning* t) {
 }
 
 asi_status asi_tune(asi_handle h, int64_t sample_steps, asi_tuning* out) {
+  Range range("asi_tune");
   asi_status st = check_handle(h);
   if (st != ASI_OK) return st;
   if (h->K <= 0) return fail(ASI_ESTATE, "no field protocol set");
@@ -1180,6 +1195,7 @@ asi_status asi_tune(asi_handle h, int64_t sample_steps, asi_tuning* out) {
 }
 
 asi_status asi_compute_fields(asi_handle h, int64_t t) {
+  Range range("asi_compute_fields");
   asi_status st = check_handle(h);
   if (st != ASI_OK) return st;
   if (t < -1 || t >= h->K) return fail(ASI_EINVAL, "step outside the protocol");
@@ -1400,6 +1416,7 @@ asi_status table_capture(Table& T, hipStream_t st) {
 
 extern "C" asi_status asi_batch_run(asi_handle* hs, int32_t count, int32_t mode,
                                     int64_t* flips_out) {
+  Range range("asi_batch_run");
   if (!hs || count < 1) return fail(ASI_EINVAL, "no handles");
   if (mode < 0 || mode > 2) return fail(ASI_EINVAL, "batch mode must be 0, 1 or 2");
   for (int32_t k = 0; k < count; ++k) {
@@ -1775,6 +1792,7 @@ asi_status asi_server_submit_fields(asi_server_t S, const asi_params* p, int64_t
 }
 
 asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out) {
+  Range range("asi_server_step");
   if (!S) return fail(ASI_EINVAL, "null server");
   if (!(budget_ms > 0.0)) return fail(ASI_EINVAL, "budget_ms must be > 0");
   int32_t resident = 0;
