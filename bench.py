@@ -38,6 +38,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+T_START = time.perf_counter()
+
+
 def progress(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 METRIC = "neighbour interactions/s & flips/s; batched/served runs/s + p99 vs plain"
@@ -431,7 +434,8 @@ def bench_served(args, asi, workloads, torch):
         r = res[j.job]
         progress(f"slow job {j.job} {j.family} n={wls[j.job].n} d={j.d:g} steps={j.n_steps} "
                  f"flips={r['flips']} served={r['t_done'] - r['t_admit']:.3f}s")
-    # plain rate from a seeded uniform sample, each job alone
+    # plain rate from a seeded uniform sample, each job alone; the sample
+    # stops early once the whole benchmark has used its time budget
     rng = np.random.default_rng(55)
     k = min(args.plain_sample, len(jobs))
     sample = sorted(rng.choice(len(jobs), size=k, replace=False).tolist())
@@ -439,6 +443,11 @@ def bench_served(args, asi, workloads, torch):
     times = []
     t1 = time.perf_counter()
     for c, q in enumerate(sample):
+        if c >= 8 and time.perf_counter() - T_START > args.time_budget_s:
+            progress(f"plain sample stopped at {c}/{k} jobs: time budget "
+                     f"{args.time_budget_s:.0f}s reached")
+            sample = sample[:c]
+            break
         j = jobs[q]
         w = wls[j.job]
         torch.cuda.synchronize()
@@ -469,13 +478,107 @@ def bench_served(args, asi, workloads, torch):
                        "parallelism": "continuous batching, one GPU"},
             "served_runs_per_s": len(jobs) / t_all, "served_seconds": t_all,
             "plain_runs_per_s": 1.0 / mean_plain,
-            "plain_sample": {"jobs": k, "mean_s": mean_plain, "max_s": float(np.max(times)),
-                             "seed": 55, "how": "uniform sample, each job alone with asi_run"},
+            "plain_sample": {"jobs": len(times), "asked": k, "mean_s": mean_plain,
+                             "max_s": float(np.max(times)), "seed": 55,
+                             "how": "uniform sample, each job alone with asi_run"},
             "speedup_vs_plain": (len(jobs) / t_all) * mean_plain,
             "latency_s": {"p50": float(np.percentile(lats, 50)),
                           "p99": float(np.percentile(lats, 99)), "max": float(lats.max())},
-            "bitwise_identical_to_plain": bool(same), "bitwise_checked_jobs": k,
+            "bitwise_identical_to_plain": bool(same), "bitwise_checked_jobs": len(times),
             "server_stats": stats}
+
+
+def _oracle_instance(spec):
+    """One sweep instance's whole protocol on the single-threaded oracle
+    (process-pool worker): (index, seconds, flips, neighbour pairs)."""
+    k, K = spec
+    from oracle import native
+    from paper_2002_11401_amd import workloads
+    w = workloads.batched_sweep(count=256, seed=4, n_steps=K)[k]
+    t0 = time.perf_counter()
+    o = native.Oracle.from_workload(w)
+    o.set_spins(w.spin0)
+    r = o.run(w.H, 0, w.n_steps, log_cap=1024)
+    dt = time.perf_counter() - t0
+    E = o.num_edges
+    o.close()
+    return k, dt, int(r["n_flips"]), E
+
+
+def bench_oracle(args, asi, workloads, torch):
+    """CPU baseline table: the single-threaded C++ oracle on this machine's
+    host cores.  For the square 10 x 10, the 100 x 100 pinwheel and the 1M
+    kagome: one full field evaluation (neighbour interactions/s, median of
+    3) and the whole protocol (wall time, flips/s, printed in chunks of
+    steps).  For the 256-instance sweep: every instance's whole protocol in
+    a process pool over the host cores (per-instance single-core seconds
+    and the pool's aggregate runs/s)."""
+    import multiprocessing as mp
+    from oracle import native
+    out = {"metric": "oracle baseline (CPU, single-threaded per instance)", "host": host_info(),
+           "configs": {}}
+    try:
+        import subprocess
+        out["host"]["lscpu"] = [ln for ln in subprocess.run(
+            ["lscpu"], capture_output=True, text=True, timeout=30).stdout.splitlines()
+            if ln.split(":")[0] in ("Model name", "CPU(s)", "Thread(s) per core",
+                                    "Core(s) per socket", "Socket(s)", "CPU max MHz",
+                                    "L3 cache", "NUMA node(s)")]
+    except Exception:  # noqa: BLE001 - informational only
+        pass
+    for name in ("square10_triangle", "pinwheel100_reversal", "kagome577_rotating"):
+        w = workloads.NAMED[name]()
+        t0 = time.perf_counter()
+        o = native.Oracle.from_workload(w)
+        t_build = time.perf_counter() - t0
+        E = o.num_edges
+        evals = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            o.set_spins(w.spin0)
+            o.fields(w.H, 0)
+            evals.append(time.perf_counter() - t0)
+        t_eval = float(np.median(evals))
+        o.set_spins(w.spin0)
+        flips, fnv = 0, native.FNV_OFFSET
+        chunk = max(1, w.n_steps // 20)
+        t0 = time.perf_counter()
+        for a in range(0, w.n_steps, chunk):
+            r = o.run(w.H, a, min(w.n_steps, a + chunk), log_cap=1024, fnv=fnv)
+            flips += int(r["n_flips"])
+            fnv = r["hash"]
+            progress(f"oracle {name}: steps ..{min(w.n_steps, a + chunk)} flips {flips} "
+                     f"{time.perf_counter() - t0:.1f}s")
+        dt = time.perf_counter() - t0
+        o.close()
+        out["configs"][name] = {"magnets": w.n, "neighbour_pairs": E, "steps": w.n_steps,
+                                "build_s": t_build, "full_evaluation_s": t_eval,
+                                "neighbour_interactions_per_s": E / t_eval,
+                                "field_calcs_per_s": w.n / t_eval,
+                                "whole_run_s": dt, "flips": flips, "flips_per_s": flips / dt,
+                                "flip_hash": str(fnv)}
+    K = 500
+    procs = min(args.oracle_procs, os.cpu_count() or 1)
+    specs = [(k, K) for k in range(args.count)]
+    t0 = time.perf_counter()
+    per = {}
+    with mp.get_context("fork").Pool(procs) as pool:
+        for k, dt, nf, E in pool.imap_unordered(_oracle_instance, specs):
+            per[k] = (dt, nf, E)
+            if len(per) % 16 == 0:
+                progress(f"oracle sweep {len(per)}/{len(specs)} {time.perf_counter() - t0:.1f}s")
+    wall = time.perf_counter() - t0
+    secs = np.array([per[k][0] for k in sorted(per)])
+    out["configs"]["batched_sweep"] = {
+        "instances": len(per), "steps": K, "processes": procs,
+        "pool_wall_s": wall, "pool_runs_per_s": len(per) / wall,
+        "single_core_sum_s": float(secs.sum()),
+        "single_core_runs_per_s": len(per) / float(secs.sum()),
+        "per_instance_s": {"min": float(secs.min()), "median": float(np.median(secs)),
+                           "max": float(secs.max())},
+        "flips": int(sum(v[1] for v in per.values())),
+        "neighbour_pairs": int(sum(v[2] for v in per.values()))}
+    return out
 
 
 def main():
@@ -483,7 +586,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--mode", choices=["all", "plain", "batched", "served", "analysis"],
+    ap.add_argument("--mode", choices=["all", "plain", "batched", "served", "analysis", "oracle"],
                     default="all")
     ap.add_argument("--workload", default="kagome577_rotating")
     ap.add_argument("--local-field", default="none", choices=["none", "gradient", "wave"],
@@ -491,11 +594,16 @@ def main():
                          "evaluated on the device (no CPU baseline for the wave)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--count", type=int, default=256, help="batched: instances")
+    ap.add_argument("--oracle-procs", type=int, default=16,
+                    help="oracle: worker processes for the sweep (at most the host's cores)")
     ap.add_argument("--batch-mode", default="fused", choices=["lockstep", "graph", "fused"])
     ap.add_argument("--tune-steps", type=int, default=20,
                     help="batched: autotune each instance on this many steps (0: off)")
     ap.add_argument("--jobs", type=int, default=2000, help="served: jobs")
-    ap.add_argument("--plain-sample", type=int, default=64, help="served: jobs re-run alone")
+    ap.add_argument("--plain-sample", type=int, default=32, help="served: jobs re-run alone")
+    ap.add_argument("--time-budget-s", type=float, default=480.0,
+                    help="served: stop the plain sample (after at least 8 jobs) once the "
+                         "benchmark has run this long")
     ap.add_argument("--rate", type=float, default=50.0, help="served: arrivals per second")
     ap.add_argument("--max-n", type=float, default=1e6, help="served: largest job")
     ap.add_argument("--slots", type=int, default=256, help="served: resident jobs")
@@ -508,14 +616,19 @@ def main():
               "communication, but no multi-GPU path is implemented.", file=sys.stderr)
         sys.exit(2)
 
+    from paper_2002_11401_amd import workloads
+    if args.mode == "oracle":
+        # host cores only: the GPU is not touched (the pool forks)
+        print(json.dumps(bench_oracle(args, None, workloads, None)), flush=True)
+        return
     import torch
-    from paper_2002_11401_amd import asi, workloads
+    from paper_2002_11401_amd import asi
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.mode != "all":
         fn = {"plain": bench_plain, "batched": bench_batched, "served": bench_served,
-              "analysis": bench_analysis}[args.mode]
+              "analysis": bench_analysis, "oracle": bench_oracle}[args.mode]
         print(json.dumps(fn(args, asi, workloads, torch)), flush=True)
         return
     # the default: the 1M-magnet kagome (value and roofline), then the
