@@ -296,13 +296,20 @@ typedef struct {
                            <= 128)                                           */
   double default_ms;    /* asi_tune: sample time with the shapes it found    */
   double tuned_ms;      /* asi_tune: sample time with the shapes it chose    */
-  int32_t trials;       /* asi_tune: shapes timed                            */
-  int32_t pad;
+  int32_t trials;       /* asi_tune: shapes timed (0: taken from the cache)  */
+  int32_t field_rows;   /* rows per workgroup of the full-field pass at >= 128
+                           neighbours (field_mode 2): 8, 16, 32 or 64; 0 =
+                           chosen by the instance size                      */
 } asi_tuning;
 /* Autotuner: times the next sample_steps (>= 1, clipped to the protocol)
- * field steps under candidate shapes (speculation threshold, then tile
- * size, then workgroup size), each run from a device snapshot of the
- * handle's state, and keeps the fastest.  Every trial must reproduce the
+ * field steps under candidate shapes (rows per workgroup of the
+ * high-degree full-field pass, speculation threshold, then tile size, then
+ * workgroup size), each run from a device snapshot of the handle's state,
+ * and keeps the fastest.  The result is cached per (GPU architecture,
+ * floor(log2 n), floor(log2 max_degree), field_mode): a later call on a
+ * handle of the same class applies the cached shapes without timing
+ * (trials = 0).  ASI_TUNE_CACHE=<file> keeps the cache in a text file
+ * across processes; ASI_TUNE_NOCACHE=1 always times.  Every trial must reproduce the
  * first trial's flip count and hash, else ASI_ESTATE.  The state, cursor
  * and flip log are restored exactly; out (may be NULL) receives the choice.
  * The snapshot is allocated through the handle's device allocator.

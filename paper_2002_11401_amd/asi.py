@@ -75,7 +75,7 @@ class AsiTiming(C.Structure):
 class AsiTuning(C.Structure):
     _fields_ = [("relax_waves", C.c_int32), ("l1_shift", C.c_int32), ("spec_min", C.c_int64),
                 ("default_ms", C.c_double), ("tuned_ms", C.c_double), ("trials", C.c_int32),
-                ("pad", C.c_int32)]
+                ("field_rows", C.c_int32)]
 
 
 class AsiServerStats(C.Structure):
@@ -435,15 +435,21 @@ class Sim:
         the state is left exactly as it was."""
         t = AsiTuning()
         _check(library().asi_tune(self.handle, int(sample_steps), C.byref(t)))
-        return {name: getattr(t, name) for name, _ in AsiTuning._fields_ if name != "pad"}
+        return {name: getattr(t, name) for name, _ in AsiTuning._fields_}
 
     def tuning(self) -> dict:
         t = AsiTuning()
         _check(library().asi_get_tuning(self.handle, C.byref(t)))
-        return {name: getattr(t, name) for name in ("relax_waves", "l1_shift", "spec_min")}
+        return {name: getattr(t, name)
+                for name in ("relax_waves", "l1_shift", "spec_min", "field_rows")}
 
-    def set_tuning(self, relax_waves: int, l1_shift: int, spec_min: int):
-        t = AsiTuning(relax_waves=int(relax_waves), l1_shift=int(l1_shift), spec_min=int(spec_min))
+    def set_tuning(self, relax_waves: int, l1_shift: int, spec_min: int,
+                   field_rows: Optional[int] = None):
+        """Set the launch shapes (field_rows None: keep the current one)."""
+        if field_rows is None:
+            field_rows = self.tuning()["field_rows"]
+        t = AsiTuning(relax_waves=int(relax_waves), l1_shift=int(l1_shift), spec_min=int(spec_min),
+                      field_rows=int(field_rows))
         _check(library().asi_set_tuning(self.handle, C.byref(t)))
 
     def set_timing(self, on: bool = True):

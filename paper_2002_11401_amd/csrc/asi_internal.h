@@ -181,8 +181,9 @@ void launch_neighbour_fill(const double* x, const double* y, const double* mx, c
 // Degree from which a single instance's full-field pass (every row
 // gathered) uses one workgroup per 64-row slice instead of one lane per row.
 constexpr int kHdMinD = 128;
-// Full-field pass of one instance of degree >= kHdMinD (field_mode full).
-void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, hipStream_t st);
+// Full-field pass of one instance of degree >= kHdMinD (field_mode full),
+// `rows` rows per workgroup (8, 16, 32 or 64; 0: chosen by the size).
+void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, int32_t rows, hipStream_t st);
 // Grid-wide field pass for every active instance of the table; rebuilds the
 // relax structures of every paused one.
 void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,

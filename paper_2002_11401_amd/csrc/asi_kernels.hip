@@ -721,6 +721,9 @@ struct RelaxShared {
   uint32_t pay;
   // predicted next flip: high 32 bits of the best updated key, then its index
   unsigned long long pfk;
+  // runner-up of the tree before the flip (j's own tile left out), packed the
+  // same way; 0 when none is known
+  unsigned long long ruk;
 };
 
 // True once the deadline (device constant-rate clock; 0: none) has passed.
@@ -1592,6 +1595,7 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
     sh.n2 = 0;
     sh.nr = 0;
     sh.pfk = 0ull;
+    sh.ruk = 0ull;
   }
   __syncthreads();
   for (int g = wave; g < nt2; g += NW) {
@@ -1728,6 +1732,32 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
         }
       }
     }
+    // Runner-up hint, by the last wavefront when it updates no neighbour:
+    // the best magnet of the tree outside j's tile (the other groups' maxima,
+    // then the other tiles of j's group), the usual next flip when no update
+    // beats it.  Read while the tree is unchanged since the root.
+    if (wave == NW - 1 && D <= (NW - 1) * 64) {
+      const int ej = (int)(j >> l1s), gj = ej / kL2Group;
+      double rk = 0.0;
+      uint32_t rp = 0;
+      for (int u = 0; u < per2; ++u) {
+        const int g = lane * per2 + u;
+        if (g < nt2 && g != gj && L.l2k[g] > rk) {
+          rk = L.l2k[g];
+          rp = L.l2i[g];
+        }
+      }
+      const int e = gj * kL2Group + lane;
+      if (e < nt1 && e != ej && L.l1k[e] > rk) {
+        rk = L.l1k[e];
+        rp = L.l1i[e];
+      }
+      wave_argmax(rk, rp);
+      if (lane == 0)
+        sh.ruk = rk > 0.0 ? (((unsigned long long)__double_as_longlong(rk) & 0xffffffff00000000ull) |
+                             (unsigned long long)(rp & 0x7fffffffu))
+                          : 0ull;
+    }
     // the flipped magnet's own stores, issued after the neighbour loads so
     // that waiting for those loads does not wait for these
     if (tid == 0) {
@@ -1744,7 +1774,9 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
                              (unsigned long long)tb_i);
     __syncthreads();
     {
-      const unsigned long long pk = sh.pfk;
+      // the next flip is probably the better of the best updated neighbour
+      // and the runner-up (compared on the keys' high bits)
+      const unsigned long long pk = sh.pfk > sh.ruk ? sh.pfk : sh.ruk;
       pf_j = pk ? (int64_t)(pk & 0xffffffffull) : -1;
       if (pf_j >= 0) {
 #pragma unroll
@@ -2513,11 +2545,12 @@ void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,
                      blk_inst, blk_row0);
 }
 
-void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, hipStream_t st) {
-  // rows per workgroup: the largest that still gives the device about four
-  // workgroups per compute unit, at least 8
+void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, int32_t rows, hipStream_t st) {
+  // rows per workgroup: by default the largest that still gives the device
+  // about four workgroups per compute unit, at least 8
   const int64_t nsl = (n + 63) / 64;
-  const int R = nsl >= 1024 ? 64 : 2 * nsl >= 1024 ? 32 : 4 * nsl >= 1024 ? 16 : 8;
+  const int R = rows ? rows
+                     : nsl >= 1024 ? 64 : 2 * nsl >= 1024 ? 32 : 4 * nsl >= 1024 ? 16 : 8;
   const unsigned blocks = (unsigned)(((nsl + 7) / 8) * 8 * (64 / R));
   switch (R) {
     case 64:

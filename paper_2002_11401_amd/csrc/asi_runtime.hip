@@ -6,12 +6,14 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
 #include <string>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/asi.h"
@@ -100,6 +102,7 @@ struct asi_sim {
   DevMem mem;
   int64_t n = 0, E = 0;
   int32_t D = 0, l1s = 6, relax_waves = 1;
+  int32_t field_rows = 0;       // rows per workgroup of the high-degree pass (0: by size)
   size_t lds = 0;
   InstDev hI{};
   InstDev* dI = nullptr;
@@ -165,7 +168,7 @@ void field_pass(asi_sim* s) {
     (void)hipEventRecord(tp.a, s->stream);
   }
   if (s->hI.field_mode == kFieldFull && s->D >= kHdMinD)
-    launch_field_hd(s->dI, s->dR, s->n, s->stream);
+    launch_field_hd(s->dI, s->dR, s->n, s->field_rows, s->stream);
   else
     launch_field(s->dI, s->dR, s->blk_inst, s->blk_row0, s->nblocks, s->stream);
   if (s->timing) {
@@ -1015,11 +1018,14 @@ asi_status asi_run(asi_handle h, int64_t t_begin, int64_t t_end, int64_t* flips_
 }
 
 static bool tuning_valid(const asi_sim* h, const asi_tuning* t) {
+  const int32_t r = t->field_rows;
   return t->relax_waves >= 1 && t->relax_waves <= kMaxRelaxWaves &&
-         t->l1_shift >= relax_l1_shift(h->n) && t->l1_shift <= 20 && t->spec_min >= 1;
+         t->l1_shift >= relax_l1_shift(h->n) && t->l1_shift <= 20 && t->spec_min >= 1 &&
+         (r == 0 || r == 8 || r == 16 || r == 32 || r == 64);
 }
 
 static asi_status apply_tuning(asi_sim* h, const asi_tuning* t) {
+  h->field_rows = t->field_rows;
   h->relax_waves = t->relax_waves;
   h->l1s = t->l1_shift;
   h->hI.l1_shift = t->l1_shift;
@@ -1036,8 +1042,105 @@ asi_status asi_get_tuning(asi_handle h, asi_tuning* out) {
   out->relax_waves = h->relax_waves;
   out->l1_shift = h->l1s;
   out->spec_min = h->hI.spec_min;
+  out->field_rows = h->field_rows;
   return ASI_OK;
 }
+
+}  // extern "C"
+
+// ---- tuning cache: shapes found by asi_tune, keyed by the device
+// architecture and the instance's size class, reused by later asi_tune calls
+// on similar instances (any shapes give the same results; only speed
+// differs).  Optionally persisted in the text file named by ASI_TUNE_CACHE;
+// ASI_TUNE_NOCACHE=1 disables lookups.
+namespace {
+
+struct TuneKey {
+  std::string arch;
+  int32_t n_bucket, d_bucket, mode;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(arch, n_bucket, d_bucket, mode) <
+           std::tie(o.arch, o.n_bucket, o.d_bucket, o.mode);
+  }
+};
+struct TuneVal {
+  int32_t relax_waves, l1_delta, field_rows;
+  int64_t spec_min;
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune_cache;
+bool g_tune_loaded = false;
+
+int32_t log2_bucket(int64_t v) {
+  int32_t b = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+TuneKey tune_key(const asi_sim* h) {
+  TuneKey k{"", log2_bucket(h->n), log2_bucket(std::max<int32_t>(h->D, 1)), h->hI.field_mode};
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) k.arch = prop.gcnArchName;
+  const size_t c = k.arch.find(':');  // feature suffixes (e.g. ":sramecc+") do not matter
+  if (c != std::string::npos) k.arch.resize(c);
+  return k;
+}
+
+// Caller holds g_tune_mu.
+void tune_cache_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("ASI_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char arch[64];
+  int nb, db, mode, w, dl, fr;
+  long long sm;
+  while (std::fscanf(f, "%63s %d %d %d %d %d %lld %d", arch, &nb, &db, &mode, &w, &dl, &sm,
+                     &fr) == 8)
+    g_tune_cache[TuneKey{arch, nb, db, mode}] = TuneVal{w, dl, fr, (int64_t)sm};
+  std::fclose(f);
+}
+
+bool tune_cache_get(const asi_sim* h, asi_tuning* t) {
+  if (const char* e = std::getenv("ASI_TUNE_NOCACHE"))
+    if (e[0] == '1') return false;
+  const TuneKey k = tune_key(h);
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_cache_load();
+  auto it = g_tune_cache.find(k);
+  if (it == g_tune_cache.end()) return false;
+  *t = asi_tuning{};
+  t->relax_waves = it->second.relax_waves;
+  t->l1_shift = relax_l1_shift(h->n) + it->second.l1_delta;
+  t->spec_min = it->second.spec_min;
+  t->field_rows = it->second.field_rows;
+  return tuning_valid(h, t);
+}
+
+void tune_cache_put(const asi_sim* h, const asi_tuning& t) {
+  const TuneKey k = tune_key(h);
+  const TuneVal v{t.relax_waves, t.l1_shift - relax_l1_shift(h->n), t.field_rows, t.spec_min};
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_cache_load();
+  g_tune_cache[k] = v;
+  const char* path = std::getenv("ASI_TUNE_CACHE");
+  if (!path || !*path) return;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%s %d %d %d %d %d %lld %d\n", k.arch.c_str(), k.n_bucket, k.d_bucket,
+                 k.mode, v.relax_waves, v.l1_delta, (long long)v.spec_min, v.field_rows);
+    std::fclose(f);
+  }
+}
+
+}  // namespace
+
+extern "C" {
 
 asi_status asi_set_tuning(asi_handle h, const asi_tuning* t) {
   asi_status st = check_handle(h);
@@ -1058,6 +1161,17 @@ asi_status asi_tune(asi_handle h, int64_t sample_steps, asi_tuning* out) {
   const int64_t t0 = h->cur_step + 1;
   if (t0 >= h->K) return fail(ASI_EINVAL, "no protocol step left to sample");
   const int64_t t1 = std::min(h->K, t0 + std::max<int64_t>(sample_steps, 1));
+  {
+    asi_tuning cached{};
+    if (tune_cache_get(h, &cached)) {  // a similar instance was tuned before
+      HIPCHK(hipStreamSynchronize(h->stream), h);
+      st = apply_tuning(h, &cached);
+      if (st == ASI_OK) st = sync_and_check(h);
+      if (st != ASI_OK) return st;
+      if (out) *out = cached;  // trials == 0: taken from the cache
+      return ASI_OK;
+    }
+  }
   const int64_t n = h->n, nsl = (n + kSlice - 1) / kSlice;
   InstDev& I = h->hI;
   // the mutable state a step reads or writes (the candidate pool is rebuilt
@@ -1152,6 +1266,16 @@ asi_status asi_tune(asi_handle h, int64_t sample_steps, asi_tuning* out) {
     }
     return ASI_OK;
   };
+  // 0. rows per workgroup of the high-degree full-field pass
+  if (st == ASI_OK && I.field_mode == kFieldFull && h->D >= kHdMinD) {
+    const int32_t rows[] = {8, 16, 32, 64};
+    for (int32_t r : rows) {
+      if (st != ASI_OK) break;
+      asi_tuning c = best;
+      c.field_rows = r;
+      st = consider(c);
+    }
+  }
   // 1. speculation threshold (only where the degree allows speculation)
   if (st == ASI_OK && h->D <= kSpecMaxD && cur.relax_waves == kMaxRelaxWaves) {
     const int64_t mins[] = {8, 256, INT64_MAX};
@@ -1185,6 +1309,7 @@ asi_status asi_tune(asi_handle h, int64_t sample_steps, asi_tuning* out) {
   h->timing = timing0;
   if (st != ASI_OK) return st;
   if (st2 != ASI_OK) return st2;
+  tune_cache_put(h, best);
   if (out) {
     *out = best;
     out->default_ms = default_ms;
@@ -1600,6 +1725,7 @@ struct asi_server {
   int64_t clock_hz = 100000000;  // device constant-rate clock
   int64_t big_magnets = 0;       // see kBigMagnets
   int32_t tail_jobs = 0;         // see kTailJobs
+  double quiet_scale = 1.0;      // see kQuietBurstScale
   asi_server_stats stats{};
 };
 
@@ -1612,6 +1738,11 @@ namespace {
 // and one relax step of every job, until the budget is spent.
 constexpr int64_t kBigMagnets = 1 << 17;
 constexpr int32_t kTailJobs = 8;
+// In the tail regime with nothing queued, a burst runs kQuietBurstScale
+// times the asked budget: bursts exist to bound how long an arriving job
+// waits for admission, and each burst boundary pauses the running relaxes,
+// whose resume rebuilds their candidate structures.
+constexpr double kQuietBurstScale = 8.0;
 
 asi_status server_rebuild(asi_server* S) {
   std::vector<InstDev> insts(S->max_slots);
@@ -1730,6 +1861,11 @@ asi_status asi_server_create(const asi_device* dev, size_t hbm_budget_bytes, int
   S->T.mem.dev = S->dev;
   S->big_magnets = kBigMagnets;
   S->tail_jobs = kTailJobs;
+  S->quiet_scale = kQuietBurstScale;
+  if (const char* v = std::getenv("ASI_SERVER_QUIET_SCALE")) {
+    const double q = std::atof(v);
+    if (q >= 1.0 && q <= 1000.0) S->quiet_scale = q;
+  }
   if (const char* v = std::getenv("ASI_SERVER_BIG")) {  // threshold overrides
     const long long b = std::atoll(v);
     if (b >= 1) S->big_magnets = b;
@@ -1820,8 +1956,9 @@ asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out
     // deadline.  In the tail regime the first round is launched here, the
     // others after admission.
     const double t_burst = now_s();
-    const int64_t ticks = std::max<int64_t>(1, (int64_t)(budget_ms * 1e-3 * (double)S->clock_hz));
     tail = resident <= S->tail_jobs && max_n >= S->big_magnets;
+    if (tail && S->queue.empty()) budget_ms *= S->quiet_scale;
+    const int64_t ticks = std::max<int64_t>(1, (int64_t)(budget_ms * 1e-3 * (double)S->clock_hz));
     launch_field(S->T.dI, S->T.dR, S->T.blk_inst, S->T.blk_row0, S->T.nblocks, S->stream);
     launch_fused(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, tail ? 1 : INT64_MAX, ticks,
                  1, S->stream);

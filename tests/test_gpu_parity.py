@@ -5,6 +5,7 @@ Bar: flip sequences (step, magnet) and final spins bit-exact; fields within
 (cancellation makes |h_i| itself a poor denominator).
 """
 import dataclasses
+import os
 import sys
 
 import numpy as np
@@ -382,7 +383,11 @@ def test_tune_restores_state_and_keeps_results(family, d, thermal):
     s.run(0, 40)
     s0, hp0, hq0, st0 = s.state()
     l0 = s.flip_log(cap=0)
-    res = s.tune(sample_steps=30)
+    os.environ["ASI_TUNE_NOCACHE"] = "1"   # time the trials even if a similar class was tuned
+    try:
+        res = s.tune(sample_steps=30)
+    finally:
+        del os.environ["ASI_TUNE_NOCACHE"]
     say("tuning", res)
     assert res["trials"] >= 3 and res["tuned_ms"] <= res["default_ms"]
     # state, cursor and log exactly as before
@@ -406,6 +411,57 @@ def test_tune_restores_state_and_keeps_results(family, d, thermal):
     s3.run()
     l3 = s3.flip_log(cap=0)
     assert (l3["count"], l3["hash"]) == (lr["count"], lr["hash"])
+
+
+def test_tune_field_rows_and_cache(tmp_path):
+    """Full-field mode at >= 128 neighbours: the tuner also times the rows
+    per workgroup of the high-degree pass; every choice, tuned or set by
+    hand, gives the reference run's flips bit for bit.  A second handle of
+    the same size class takes the shapes from the cache without timing, and
+    the cache file gets the entry."""
+    xy, theta = W.pinwheel_diamond(45)
+    n = len(theta)
+    H = W.linear_ramp(60, 0.1, -0.1, 30.0)
+    w = W.Workload("pinwheel45", xy, theta, W.polarised_spins(theta, H[0]),
+                   W.disorder_hk(n, 0.2, 0.05, 11), H, alpha=0.0013, neighbor_distance=8.0,
+                   b=0.38, c=1, beta=1.5, gamma=3.9, thermal_std=0.002, thermal_seed=6)
+    ref = gpu_sim(w, field_mode="full")
+    assert ref.info()["max_degree"] >= 128
+    ref.run()
+    lr = ref.flip_log(cap=0)
+    cache = tmp_path / "tune_cache.txt"
+    os.environ["ASI_TUNE_NOCACHE"] = "1"
+    os.environ["ASI_TUNE_CACHE"] = str(cache)
+    try:
+        a = gpu_sim(w, field_mode="full")
+        ra = a.tune(sample_steps=10)
+    finally:
+        del os.environ["ASI_TUNE_NOCACHE"]
+    try:
+        say("tuned", ra)
+        assert ra["trials"] >= 5 and ra["field_rows"] in (0, 8, 16, 32, 64)
+        line = cache.read_text().split()
+        assert len(line) == 8 and line[0].startswith("gfx")
+        b = gpu_sim(w, field_mode="full")
+        rb = b.tune(sample_steps=10)
+        assert rb["trials"] == 0
+        assert {k: rb[k] for k in ("relax_waves", "l1_shift", "spec_min", "field_rows")} == \
+            {k: ra[k] for k in ("relax_waves", "l1_shift", "spec_min", "field_rows")}
+    finally:
+        del os.environ["ASI_TUNE_CACHE"]
+    for s in (a, b):
+        s.run()
+        la = s.flip_log(cap=0)
+        assert (la["count"], la["hash"]) == (lr["count"], lr["hash"])
+    for rows in (8, 16, 32, 64):
+        c = gpu_sim(w, field_mode="full")
+        t = c.tuning()
+        c.set_tuning(t["relax_waves"], t["l1_shift"], t["spec_min"], rows)
+        c.run()
+        lc = c.flip_log(cap=0)
+        assert (lc["count"], lc["hash"]) == (lr["count"], lr["hash"]), rows
+    with pytest.raises(asi.AsiError):
+        c.set_tuning(t["relax_waves"], t["l1_shift"], t["spec_min"], 12)
 
 
 def test_tuned_instances_batch_bitwise():
