@@ -173,6 +173,23 @@ def bench_plain(args, asi, workloads, torch):
     if Wu > 0:
         sim.run(0, Wu)
     progress(f"{w.name}: {N} magnets, {E} pairs; warm-up {Wu} steps done")
+    if args.no_full_protocol:
+        # counter runs: only the first K steps, from the start state
+        sim.set_state(w.spin0, -1)
+        sim.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        flips = sim.run(0, K)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tm = sim.timing()
+        sim.close()
+        fa = tm["field_ms"] / max(1, tm["field_launches"]) / 1e3
+        return {"metric": METRIC, "value": E * K / dt, "unit": "neighbour interactions/s",
+                "steps": K, "flips": flips, "config": {"workload": w.name, "timed_steps": f"0..{K - 1}"},
+                "field_pass": {"avg_us": fa * 1e6, "launches": tm["field_launches"],
+                               "algorithmic_bytes": info["field_pass_bytes"]},
+                "note": "--no-full-protocol: first K steps only (counter runs)"}
     # the whole protocol, timed once
     sim.set_state(w.spin0, -1)
     sim.set_timing(True)
@@ -593,6 +610,8 @@ def main():
                     help="plain: add a static spatial field, or a travelling wave "
                          "evaluated on the device (no CPU baseline for the wave)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full-protocol", action="store_true",
+                    help="plain: time only the first K steps (for counter runs)")
     ap.add_argument("--count", type=int, default=256, help="batched: instances")
     ap.add_argument("--oracle-procs", type=int, default=16,
                     help="oracle: worker processes for the sweep (at most the host's cores)")
