@@ -397,10 +397,13 @@ asi_status asi_server_destroy(asi_server_t s);
  * wavefront each follow a pointer chain through a buffer of `bytes` bytes
  * (one 4-byte element per 128-byte line, the lines in one random cycle drawn
  * from `seed`, built and checked on the host; lane l starts l/64 of the way
- * round), `hops` loads each, timed with the device's constant-rate clock.
+ * round), `hops` loads each, timed with the device's constant-rate clock,
+ * after a first untimed pass (the whole cycle for buffers of at most 64 MiB,
+ * else `hops` loads per lane) that the timed pass continues.
  * With lanes = 1 a hop is one load; with 64 it is one scattered 64-address
- * gather.  A buffer that fits the L2 (a few MB) gives the L2 latency, one far
- * beyond the 256 MB last-level cache the HBM latency.  ns_out receives
+ * gather.  A buffer that fits the L2 (a few MB) gives the L2 latency; in one
+ * far beyond the 256 MB last-level cache every timed load is to a line not
+ * touched before, which gives the HBM latency (address translations warm).  ns_out receives
  * nanoseconds per hop.  Allocates bytes / 32 bytes through dev (NULL:
  * hipMalloc on the current device, own stream).  ASI_EINVAL unless hops >=
  * 1, 1 <= lanes <= 64 and 8 KiB <= bytes <= 2^36. */

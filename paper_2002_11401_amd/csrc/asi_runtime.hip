@@ -2092,8 +2092,30 @@ asi_status asi_measure_load_latency(const asi_device* dev, int64_t bytes, int64_
   if (e == hipSuccess)
     e = hipMemcpyAsync(dstarts, starts.data(), 4 * 64, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) {
-    // a first pass over (up to) the whole cycle warms caches and translations
-    launch_chase(dchain, dstarts, lanes, std::min<int64_t>(hops, lines), dout, st);
+    // A first pass warms the address translations: the whole cycle for a
+    // buffer of at most 64 MiB (which then sits in the caches), else `hops`
+    // steps per lane.  The timed pass continues from where each lane's first
+    // pass stopped, so in a large buffer every timed load is to a line not
+    // touched before (far beyond the last-level cache: an HBM access).
+    const int64_t warm = bytes <= ((int64_t)64 << 20) ? lines : std::min<int64_t>(hops, lines);
+    launch_chase(dchain, dstarts, lanes, warm, dout, st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 8 * 65, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) {
+    for (int l = 0; l < lanes; ++l) {
+      const unsigned long long q = out[1 + l];
+      if (q >= (unsigned long long)(lines * 32) || (q % 32) != 0) {
+        e = hipErrorUnknown;  // cannot happen: every index in the cycle is in bounds
+        break;
+      }
+      starts[l] = (int32_t)q;
+    }
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dstarts, starts.data(), 4 * 64, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
     launch_chase(dchain, dstarts, lanes, hops, dout, st);
     e = hipGetLastError();
   }

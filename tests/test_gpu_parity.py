@@ -1097,3 +1097,19 @@ def test_fused_batch_thermal_bitwise_and_oracle(mode):
             assert np.array_equal(x, y)
         o, r = oracle_run(w)
         assert_same_flips(lg, r, st[0], o.spins())
+
+
+def test_load_latency_probe_orders_cache_levels():
+    """The dependent-load probe the relax is measured against: a chase
+    through 4 MiB (warmed whole: L2) is faster than one through 1 GiB whose
+    timed loads all go to lines not touched before (HBM), and a 64-lane
+    gather is not faster than a single load."""
+    l2 = asi.load_latency_ns(4 << 20, hops=20000, lanes=1)
+    hbm = asi.load_latency_ns(1 << 30, hops=20000, lanes=1)
+    l2g = asi.load_latency_ns(4 << 20, hops=20000, lanes=64)
+    hbmg = asi.load_latency_ns(1 << 30, hops=20000, lanes=64)
+    say("latency ns", l2, hbm, l2g, hbmg)
+    assert 0 < l2 < hbm and hbm > 1.5 * l2
+    assert l2g >= 0.9 * l2 and hbmg >= 0.9 * hbm
+    with pytest.raises(asi.AsiError):
+        asi.load_latency_ns(1 << 10, hops=10, lanes=1)
