@@ -1970,7 +1970,9 @@ __device__ __forceinline__ int relax_step(const InstDev* __restrict__ I, RunDev*
 __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __restrict__ insts,
                                                               RunDev* __restrict__ runs) {
   RunDev* R = runs + blockIdx.x;
-  if (!R->active) return;
+  // a relax paused at a burst deadline finishes its step here, its
+  // structures rebuilt by the preceding field launch
+  if (!R->active && !R->paused) return;
   extern __shared__ unsigned char lds_raw[];
   __shared__ RelaxShared sh;
   __shared__ SpecShared ssh;

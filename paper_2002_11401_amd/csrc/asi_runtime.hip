@@ -1739,9 +1739,11 @@ namespace {
 constexpr int64_t kBigMagnets = 1 << 17;
 constexpr int32_t kTailJobs = 8;
 // In the tail regime with nothing queued, a burst runs kQuietBurstScale
-// times the asked budget: bursts exist to bound how long an arriving job
-// waits for admission, and each burst boundary pauses the running relaxes,
-// whose resume rebuilds their candidate structures.
+// times the asked budget, and each round relaxes every job's step to its end
+// with the relax kernel (no deadline: no pause, whose resume would rebuild
+// the candidate structures, and the relax kernel's lighter register use):
+// bursts exist to bound how long an arriving job waits for admission, and
+// none is waiting.  A round can then outlast the budget by one step's relax.
 constexpr double kQuietBurstScale = 8.0;
 
 asi_status server_rebuild(asi_server* S) {
@@ -1933,7 +1935,7 @@ asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out
   if (!(budget_ms > 0.0)) return fail(ASI_EINVAL, "budget_ms must be > 0");
   int32_t resident = 0;
   int64_t max_n = 0;
-  bool tail = false;
+  bool tail = false, quiet = false;
   double t_end = 0.0;
   for (int32_t k = 0; k < S->max_slots; ++k) {
     S->in_burst[k] = S->slots[k] >= 0;
@@ -1957,11 +1959,15 @@ asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out
     // others after admission.
     const double t_burst = now_s();
     tail = resident <= S->tail_jobs && max_n >= S->big_magnets;
-    if (tail && S->queue.empty()) budget_ms *= S->quiet_scale;
+    quiet = tail && S->queue.empty();
+    if (quiet) budget_ms *= S->quiet_scale;
     const int64_t ticks = std::max<int64_t>(1, (int64_t)(budget_ms * 1e-3 * (double)S->clock_hz));
     launch_field(S->T.dI, S->T.dR, S->T.blk_inst, S->T.blk_row0, S->T.nblocks, S->stream);
-    launch_fused(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, tail ? 1 : INT64_MAX, ticks,
-                 1, S->stream);
+    if (quiet)
+      launch_relax(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, S->stream);
+    else
+      launch_fused(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, tail ? 1 : INT64_MAX,
+                   ticks, 1, S->stream);
     HIPCHK(hipMemcpyAsync(S->rb, S->T.dR, sizeof(RunDev) * S->max_slots, hipMemcpyDeviceToHost,
                           S->stream),
            (asi_sim*)nullptr);
@@ -1990,7 +1996,10 @@ asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out
       if (!more || left <= 0.0) break;
       const int64_t ticks = std::max<int64_t>(1, (int64_t)(left * (double)S->clock_hz));
       launch_field(S->T.dI, S->T.dR, S->T.blk_inst, S->T.blk_row0, S->T.nblocks, S->stream);
-      launch_fused(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, 1, ticks, 1, S->stream);
+      if (quiet)
+        launch_relax(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, S->stream);
+      else
+        launch_fused(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, 1, ticks, 1, S->stream);
       HIPCHK(hipMemcpyAsync(S->rb, S->T.dR, sizeof(RunDev) * S->max_slots,
                             hipMemcpyDeviceToHost, S->stream),
              (asi_sim*)nullptr);

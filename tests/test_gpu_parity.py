@@ -227,6 +227,7 @@ def test_batched_equals_plain_bitwise():
     (0.002, None, 4, 10),   # below one relax batch: nearly every relax pauses
     (0.05, 1500, 4, 10),    # rounds, every job one step per round
     (0.05, 1500, 12, 24),   # rounds, jobs >= 1500 magnets one step per round
+    (0.002, 1500, 4, 10),   # paused fused relaxes finished by quiet rounds' relax kernel
 ])
 def test_served_equals_plain_bitwise(budget_ms, big, slots, count, monkeypatch):
     # paused relaxes must continue exactly where they stopped, whether their
