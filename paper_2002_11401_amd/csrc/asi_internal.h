@@ -5,6 +5,19 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+// Pointers to device memory held in the instance descriptor.  In the
+// kernels' device pass they carry the global address space, so accesses
+// through them compile to global loads and stores (a scalar base plus a
+// vector offset, counted by the vector-memory counter only) instead of flat
+// ones, whose completion every wait for an LDS access would also await.
+// Elsewhere (host code, and the runtime's device pass, which holds no
+// kernels) they are plain pointers; the layout is the same.
+#if defined(__HIP_DEVICE_COMPILE__) && defined(ASI_KERNELS_UNIT)
+#define ASI_GLOBAL __attribute__((address_space(1)))
+#else
+#define ASI_GLOBAL
+#endif
+
 namespace asi {
 
 // Rows per neighbour-table slice: one row per lane of a wavefront.
@@ -38,55 +51,55 @@ struct InstDev {
   // Neighbour tables, sliced for the field pass (one row per lane): slot k
   // of row i lives at ((i / 64) * D + k) * 64 + (i % 64);  col == -1 pads a
   // row.
-  const int32_t* len;     // [n] neighbours of each row
-  const int32_t* col;     // neighbour index j (ascending within a row)
-  const double* A;        // mhat_i    . c_ij  (symmetric: A_ij == A_ji)
-  const double* B;        // mhatperp_i. c_ij  (field at row i from j)
+  const ASI_GLOBAL int32_t* len;     // [n] neighbours of each row
+  const ASI_GLOBAL int32_t* col;     // neighbour index j (ascending within a row)
+  const ASI_GLOBAL double* A;        // mhat_i    . c_ij  (symmetric: A_ij == A_ji)
+  const ASI_GLOBAL double* B;        // mhatperp_i. c_ij  (field at row i from j)
   // The same rows row-major for the relax, which walks one row at a time
   // (a wavefront reads consecutive slots): slot k of row i at i * D + k.
-  const int32_t* rcol;    // neighbour index j, -1 pads
-  const double* rA;       // A_ij
-  const double* rBr;      // mhatperp_j. c_ji  (field at neighbour j from row i)
-  const double* mx;       // [n] easy axis mhat_i = (mx, my)
-  const double* my;
-  const double* hk;       // [n] coercive field h_k^(i)
+  const ASI_GLOBAL int32_t* rcol;    // neighbour index j, -1 pads
+  const ASI_GLOBAL double* rA;       // A_ij
+  const ASI_GLOBAL double* rBr;      // mhatperp_j. c_ji  (field at neighbour j from row i)
+  const ASI_GLOBAL double* mx;       // [n] easy axis mhat_i = (mx, my)
+  const ASI_GLOBAL double* my;
+  const ASI_GLOBAL double* hk;       // [n] coercive field h_k^(i)
   double b, c;            // astroid width parameters
   double e_par, e_perp;   // astroid exponents 2/gamma and 2/beta
   double sigma;           // thermal std
-  const double* sigma_t;  // [K] thermal std of each step (replaces sigma), or null
+  const ASI_GLOBAL double* sigma_t;  // [K] thermal std of each step (replaces sigma), or null
   uint64_t seed;          // thermal Philox key
-  const double* H;        // [K][2] applied field per step
+  const ASI_GLOBAL double* H;        // [K][2] applied field per step
   int64_t K;
-  const double2* hloc;    // [hloc_k][n] per-magnet external field (x, y), or null
+  const ASI_GLOBAL double2* hloc;    // [hloc_k][n] per-magnet external field (x, y), or null
   int64_t hloc_k;         // 1: the same field at every step; else one per step (== K)
   // travelling-wave local field evaluated in the pass: wave_amp * sin(wave_ph[i]
   // - wave_w * t) along (wave_ex, wave_ey); wave_ph null when none
-  const double* wave_ph;  // [n] 2 pi (k . r_i) + phase0
+  const ASI_GLOBAL double* wave_ph;  // [n] 2 pi (k . r_i) + phase0
   double wave_amp, wave_w, wave_ex, wave_ey;
   int32_t field_mode;     // FieldMode
   int32_t pad0;
   // mutable state
-  int8_t* s;              // [n] spins
-  uint8_t* dirty;         // [n] row's dipolar sum must be gathered at the next step
+  ASI_GLOBAL int8_t* s;              // [n] spins
+  ASI_GLOBAL uint8_t* dirty;         // [n] row's dipolar sum must be gathered at the next step
   // Field pairs (x: easy axis, y: hard axis) kept together, so the relax
   // reads or writes a magnet's pair with one 16-byte access.
-  double2* hd;            // [n] dipolar field (gathered, plus flip deltas)
-  double2* h;             // [n] total field (dipolar + applied + thermal)
-  double* key;            // [n] Eq. 5 LHS if flippable, else 0
-  double* t1key;          // [ceil(n/64)] per-64-row maximum key
-  uint32_t* t1idx;        //   its index, bit 31 set when that spin is -1
-  int32_t* log_t;         // flip log
-  int32_t* log_j;
+  ASI_GLOBAL double2* hd;            // [n] dipolar field (gathered, plus flip deltas)
+  ASI_GLOBAL double2* h;             // [n] total field (dipolar + applied + thermal)
+  ASI_GLOBAL double* key;            // [n] Eq. 5 LHS if flippable, else 0
+  ASI_GLOBAL double* t1key;          // [ceil(n/64)] per-64-row maximum key
+  ASI_GLOBAL uint32_t* t1idx;        //   its index, bit 31 set when that spin is -1
+  ASI_GLOBAL int32_t* log_t;         // flip log
+  ASI_GLOBAL int32_t* log_j;
   int64_t log_cap;
-  int32_t* step_flips;    // [K] flips of each step (may be null)
+  ASI_GLOBAL int32_t* step_flips;    // [K] flips of each step (may be null)
   int64_t max_flips;      // per relax
   // candidate pool of the speculative relax: the field phase appends every
   // flippable magnet as (key, index | sign bit, version) to buffer 0
-  uint32_t* ver;          // [n] version of each magnet's key
-  uint32_t* cpay[2];      // [ccap] pool buffers
-  double* ckey[2];
-  uint32_t* cver[2];
-  int32_t* ccount;        // entries in buffer 0 (field phase appends)
+  ASI_GLOBAL uint32_t* ver;          // [n] version of each magnet's key
+  ASI_GLOBAL uint32_t* cpay[2];      // [ccap] pool buffers
+  ASI_GLOBAL double* ckey[2];
+  ASI_GLOBAL uint32_t* cver[2];
+  ASI_GLOBAL int32_t* ccount;        // entries in buffer 0 (field phase appends)
   int64_t ccap;
   int64_t spec_min;       // flippable magnets at step start to go speculative
   double spec_switch;     // mean batch below which a speculative step goes on the tree

@@ -22,6 +22,7 @@
 #include <climits>
 #include <mutex>
 
+#define ASI_KERNELS_UNIT 1
 #include "asi_internal.h"
 
 namespace asi {
@@ -89,7 +90,10 @@ __device__ inline float pow_bound(double x, double e) {
 // normalised field components a and q whose powers decide it.
 __device__ inline bool key_needs_powers(int s, double hp, double hq, double hk, double b,
                                         double c, double ep, double eq, double& a, double& q) {
-  const bool against = (s > 0) ? (hp < 0.0) : (hp > 0.0);
+  // h_k > 0 always (checked at creation); testing it with the direction
+  // makes h_k needed on every path, so its load is issued with the field's
+  // and the spin's instead of after them
+  const bool against = (hk > 0.0) && ((s > 0) ? (hp < 0.0) : (hp > 0.0));
   if (!against) return false;
   a = fabs(hp) / (b * hk);
   q = fabs(hq) / (c * hk);
@@ -1689,6 +1693,12 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
     // lowest index among the updates holding it.
     const bool incr = D <= 2 * NT;
     const bool hit = j == pf_j;
+    // The predicted row's loads were issued before the last tile rescans,
+    // whose loads the wavefront has waited for, so they are complete; using
+    // the registers here makes that known, and no wait below is widened to
+    // them.
+    asm volatile("" ::"v"(pf_c[0]), "v"(pf_c[1]), "v"(pf_a[0]), "v"(pf_a[1]), "v"(pf_b[0]),
+                 "v"(pf_b[1]));
     int u_i[2], u_e[2], u_s[2];
     double u_k[2];
     double tb_k = 0.0;  // this thread's best updated key, for the prediction
@@ -1698,21 +1708,27 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
     for (int k = tid, h = 0; k < D; k += NT, ++h) {
       const int64_t sl = j * D + k;
       const bool pre = hit && h < 2;
+      // the slot's column and couplings together (a padding slot holds -1
+      // and zeros), then every load of the neighbour's state before any
+      // store, so that each costs one round trip
       const int32_t i = pre ? pf_c[h & 1] : colp[sl];
+      const double ca = pre ? pf_a[h & 1] : Ap[sl];
+      const double cb = pre ? pf_b[h & 1] : Brp[sl];
       if (i >= 0) {
-        const double da = two * (pre ? pf_a[h & 1] : Ap[sl]);
-        const double db = two * (pre ? pf_b[h & 1] : Brp[sl]);
         const double2 hi = hp2[i];
+        const double2 di = (mode == kFieldCarry) ? hd2[i] : make_double2(0.0, 0.0);
+        const int si = sp[i];
+        const double hki = hkp[i];
+        const double da = two * ca;
+        const double db = two * cb;
         const double hp = hi.x + da;
         const double hq = hi.y + db;
+        const double kk = switching_key(si, hp, hq, hki, pb, pc, ep, eq);
         if (mode == kFieldCarry) {
-          const double2 di = hd2[i];
           hd2[i] = make_double2(di.x + da, di.y + db);
         } else if (mode == kFieldDirty) {
           dirtyp[i] = 1;
         }
-        const int si = sp[i];
-        const double kk = switching_key(si, hp, hq, hkp[i], pb, pc, ep, eq);
         hp2[i] = make_double2(hp, hq);
         keyp[i] = kk;
         const int e = (int)(i >> l1s);
@@ -1849,12 +1865,21 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
 #pragma unroll
           for (int m = 0; m < 8; ++m) ss[m] = (int)(int8_t)(uint8_t)(s8 >> (8 * m));
         } else {
+          // short segment or the array's end: every load issued at once, an
+          // index past the segment replaced by magnet 0 and its key dropped
 #pragma unroll
           for (int m = 0; m < 8; ++m) {
             const int64_t ii = r0 + m0 + m;
-            const bool ok = m0 + m < seg && ii < n;
-            kk[m] = ok ? keyp[ii] : 0.0;
-            ss[m] = ok ? sp[ii] : 0;
+            const int64_t ic = (m0 + m < seg && ii < n) ? ii : 0;
+            kk[m] = keyp[ic];
+            ss[m] = sp[ic];
+          }
+#pragma unroll
+          for (int m = 0; m < 8; ++m) {
+            if (!(m0 + m < seg && r0 + m0 + m < n)) {
+              kk[m] = 0.0;
+              ss[m] = 0;
+            }
           }
         }
 #pragma unroll
