@@ -660,15 +660,13 @@ struct RelaxLds {
   double* l1k;                // first level: maximum key of each tile
   uint32_t* l1i;              //   its index | sign bit
   int32_t* l1flag;            //   tile touched by the current flip
-  int32_t* l1list;            //   touched tiles
   unsigned long long* l1nk;   //   largest new key of the flip's updates (bits), 0: none
   unsigned long long* l1ni;   //   lowest (index << 1 | spin<0) among updates with that key
   int32_t* l1resc;            //   the tile's maximum was updated: rescan it
   int32_t* l1rlist;           //   tiles to rescan
   double* l2k;                // second level: maximum over 64 tiles
   uint32_t* l2i;
-  int32_t* l2flag;
-  int32_t* l2list;
+  int32_t* l2flag;            //   group touched by the current flip
 };
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
@@ -681,10 +679,9 @@ __host__ __device__ inline size_t relax_tree_lds_bytes(int64_t n, int32_t l1_shi
   off = align16(off + sizeof(unsigned long long) * nt1);
   off = align16(off + sizeof(double) * nt1);
   off = align16(off + sizeof(uint32_t) * nt1);
-  for (int a = 0; a < 4; ++a) off = align16(off + sizeof(int32_t) * nt1);
+  for (int a = 0; a < 3; ++a) off = align16(off + sizeof(int32_t) * nt1);
   off = align16(off + sizeof(double) * nt2);
   off = align16(off + sizeof(uint32_t) * nt2);
-  off = align16(off + sizeof(int32_t) * nt2);
   off = align16(off + sizeof(int32_t) * nt2);
   return off;
 }
@@ -702,8 +699,6 @@ __device__ inline RelaxLds carve(unsigned char* base, int nt1, int nt2) {
   off = align16(off + sizeof(uint32_t) * nt1);
   L.l1flag = (int32_t*)(base + off);
   off = align16(off + sizeof(int32_t) * nt1);
-  L.l1list = (int32_t*)(base + off);
-  off = align16(off + sizeof(int32_t) * nt1);
   L.l1resc = (int32_t*)(base + off);
   off = align16(off + sizeof(int32_t) * nt1);
   L.l1rlist = (int32_t*)(base + off);
@@ -713,13 +708,11 @@ __device__ inline RelaxLds carve(unsigned char* base, int nt1, int nt2) {
   L.l2i = (uint32_t*)(base + off);
   off = align16(off + sizeof(uint32_t) * nt2);
   L.l2flag = (int32_t*)(base + off);
-  off = align16(off + sizeof(int32_t) * nt2);
-  L.l2list = (int32_t*)(base + off);
   return L;
 }
 
 struct RelaxShared {
-  int n1, n2, nr;
+  int nr;  // tiles to rescan
   int pause;  // the relax stops here and resumes in a later launch
   double key;
   uint32_t pay;
@@ -1595,8 +1588,6 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
     L.l1resc[e] = 0;
   }
   if (tid == 0) {
-    sh.n1 = 0;
-    sh.n2 = 0;
     sh.nr = 0;
     sh.pfk = 0ull;
     sh.ruk = 0ull;
@@ -1627,11 +1618,14 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
 
   while (true) {
     if (wave == 0) {
-      // second level of the groups the last flip touched (one wavefront:
-      // few groups per flip), then the root
-      const int n2 = sh.n2;
-      for (int u = 0; u < n2; ++u) {
-        const int g = L.l2list[u];
+      // second level of the groups the last flip touched (their flags; at
+      // most kMaxL1Tiles / kL2Group = 32 groups, one per lane), then the root
+      const bool gf = lane < nt2 && L.l2flag[lane] != 0;
+      unsigned long long gbal = __ballot(gf);
+      if (gf) L.l2flag[lane] = 0;
+      while (gbal) {
+        const int g = __ffsll(gbal) - 1;
+        gbal &= gbal - 1ull;
         const int e = g * kL2Group + lane;
         double k = (e < nt1) ? L.l1k[e] : 0.0;
         uint32_t p2 = (e < nt1) ? L.l1i[e] : 0u;
@@ -1639,7 +1633,6 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
         if (lane == 0) {
           L.l2k[g] = k;
           L.l2i[g] = p2;
-          L.l2flag[g] = 0;
         }
       }
       double bk = 0.0;
@@ -1659,7 +1652,6 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
         sh.key = bk;
         sh.pay = bp;
         sh.pause = (flips > flips0 && ((flips - flips0) & 15) == 0 && past(deadline)) ? 1 : 0;
-        sh.n2 = 0;
       }
     }
     __syncthreads();
@@ -1681,7 +1673,7 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
       hash = (hash ^ w) * 0x100000001b3ull;
       const int e = (int)(j >> l1s);
       L.l1resc[e] = 1;  // j was its tile's maximum
-      if (atomicExch(&L.l1flag[e], 1) == 0) L.l1list[atomicAdd(&sh.n1, 1)] = e;
+      L.l1flag[e] = 1;
     }
     ++logpos;
     ++flips;
@@ -1732,9 +1724,10 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
         hp2[i] = make_double2(hp, hq);
         keyp[i] = kk;
         const int e = (int)(i >> l1s);
-        if (atomicExch(&L.l1flag[e], 1) == 0) L.l1list[atomicAdd(&sh.n1, 1)] = e;
-        if (!incr || (L.l1k[e] > 0.0 && (L.l1i[e] & 0x7fffffffu) == (uint32_t)i))
-          L.l1resc[e] = 1;
+        const double ek = L.l1k[e];
+        const uint32_t ei = L.l1i[e];
+        L.l1flag[e] = 1;
+        if (!incr || (ek > 0.0 && (ei & 0x7fffffffu) == (uint32_t)i)) L.l1resc[e] = 1;
         if (kk > 0.0) atomicMax(&L.l1nk[e], (unsigned long long)__double_as_longlong(kk));
         if (kk > tb_k) {
           tb_k = kk;
@@ -1817,9 +1810,10 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
     }
     __syncthreads();
     if (tid == 0) sh.pfk = 0ull;  // every thread has read it
-    const int n1 = sh.n1;
-    for (int u = tid; u < n1; u += NT) {
-      const int e = L.l1list[u];
+    // touched tiles: a scan of the flags (nt1 <= kMaxL1Tiles), each tile's
+    // state read at once
+    for (int e = tid; e < nt1; e += NT) {
+      if (!L.l1flag[e]) continue;
       if (L.l1resc[e]) {
         L.l1rlist[atomicAdd(&sh.nr, 1)] = e;
       } else {
@@ -1834,8 +1828,7 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
           }
         }
         L.l1flag[e] = 0;
-        const int g = e / kL2Group;
-        if (atomicExch(&L.l2flag[g], 1) == 0) L.l2list[atomicAdd(&sh.n2, 1)] = g;
+        L.l2flag[e / kL2Group] = 1;
       }
       L.l1nk[e] = 0ull;
       L.l1ni[e] = ~0ull;
@@ -1896,15 +1889,11 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
         L.l1i[e] = bp;
         L.l1flag[e] = 0;
         L.l1resc[e] = 0;
-        const int g = e / kL2Group;
-        if (atomicExch(&L.l2flag[g], 1) == 0) L.l2list[atomicAdd(&sh.n2, 1)] = g;
+        L.l2flag[e / kL2Group] = 1;
       }
     }
     __syncthreads();
-    if (tid == 0) {
-      sh.n1 = 0;
-      sh.nr = 0;
-    }
+    if (tid == 0) sh.nr = 0;
   }
   return status;
 }
