@@ -29,6 +29,9 @@ constexpr int kFieldBlock = 256;
 constexpr int kMaxL1Tiles = 2048;
 // First-level tiles per second-level group (one per lane).
 constexpr int kL2Group = 64;
+// Max-tree relax: up to this many tiles the root reads the first level
+// directly (eight tiles per lane) instead of a second level.
+constexpr int kFlatTiles = 512;
 // Largest relax workgroup.
 constexpr int kMaxRelaxWaves = 16;
 // Above this degree a speculative batch holds too few members to beat the
@@ -201,9 +204,16 @@ void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, int32_t rows, 
 // relax structures of every paused one.
 void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,
                   const int32_t* blk_row0, int64_t nblocks, hipStream_t st);
-// One workgroup per instance: relax the current step.
+// One workgroup per instance: relax the current step.  tree_only when no
+// instance of the launch may speculate (see relax_may_speculate): the kernel
+// then holds the max tree alone.
 void launch_relax(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
-                  size_t lds_bytes, hipStream_t st);
+                  size_t lds_bytes, bool tree_only, hipStream_t st);
+// Whether an instance of degree D relaxed by workgroups of `waves` wavefronts
+// may take the speculative path (it needs the full 16-wavefront workgroup).
+inline bool relax_may_speculate(int32_t D, int32_t waves) {
+  return waves == kMaxRelaxWaves && D <= kSpecMaxD;
+}
 // One workgroup per instance: up to max_steps whole steps (field phase and
 // relax) per instance.  With budget_ticks > 0 a workgroup stops once that many ticks of the
 // device's constant-rate clock have passed: between steps, or inside a relax

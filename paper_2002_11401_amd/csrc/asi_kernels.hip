@@ -1529,6 +1529,7 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
 // key); the touched tiles and groups are rescanned.  Returns 0, -5 (flip
 // cap reached with a flippable magnet left) or 1 (deadline passed, checked
 // every 16 flips, with flippable magnets left).
+template <bool kFlatOk>
 __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t t, unsigned char* lds_raw,
                           RelaxShared& sh, int64_t& flips, int64_t& logpos, uint64_t& hash,
                           uint64_t deadline) {
@@ -1616,34 +1617,63 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
   int32_t pf_c[2] = {-1, -1};
   double pf_a[2] = {0.0, 0.0}, pf_b[2] = {0.0, 0.0};
 
+  // Up to kFlatTiles tiles the root reads the first level directly (at most
+  // eight ascending tiles per lane) and the second level is not kept; only
+  // in the tree-only kernel, whose registers allow it.
+  const bool flat = kFlatOk && nt1 <= kFlatTiles;
+  const int per1 = (nt1 + 63) >> 6;
+
   while (true) {
     if (wave == 0) {
-      // second level of the groups the last flip touched (their flags; at
-      // most kMaxL1Tiles / kL2Group = 32 groups, one per lane), then the root
-      const bool gf = lane < nt2 && L.l2flag[lane] != 0;
-      unsigned long long gbal = __ballot(gf);
-      if (gf) L.l2flag[lane] = 0;
-      while (gbal) {
-        const int g = __ffsll(gbal) - 1;
-        gbal &= gbal - 1ull;
-        const int e = g * kL2Group + lane;
-        double k = (e < nt1) ? L.l1k[e] : 0.0;
-        uint32_t p2 = (e < nt1) ? L.l1i[e] : 0u;
-        wave_argmax(k, p2);
-        if (lane == 0) {
-          L.l2k[g] = k;
-          L.l2i[g] = p2;
-        }
-      }
       double bk = 0.0;
       uint32_t bp = 0;
-      for (int u = 0; u < per2; ++u) {
-        const int g = lane * per2 + u;
-        if (g < nt2) {
-          const double k = L.l2k[g];
-          if (k > bk) {
-            bk = k;
-            bp = L.l2i[g];
+      if (flat) {
+        // the lane's tiles four at a time, each group's reads issued together
+        for (int u0 = 0; u0 < per1; u0 += 4) {
+          double kk[4];
+          uint32_t ii[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = lane * per1 + u0 + u;
+            const int ec = (u0 + u < per1 && e < nt1) ? e : 0;
+            kk[u] = L.l1k[ec];
+            ii[u] = L.l1i[ec];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = lane * per1 + u0 + u;
+            if (u0 + u < per1 && e < nt1 && kk[u] > bk) {
+              bk = kk[u];
+              bp = ii[u];
+            }
+          }
+        }
+      } else {
+        // second level of the groups the last flip touched (their flags; at
+        // most kMaxL1Tiles / kL2Group = 32 groups, one per lane), then the root
+        const bool gf = lane < nt2 && L.l2flag[lane] != 0;
+        unsigned long long gbal = __ballot(gf);
+        if (gf) L.l2flag[lane] = 0;
+        while (gbal) {
+          const int g = __ffsll(gbal) - 1;
+          gbal &= gbal - 1ull;
+          const int e = g * kL2Group + lane;
+          double k = (e < nt1) ? L.l1k[e] : 0.0;
+          uint32_t p2 = (e < nt1) ? L.l1i[e] : 0u;
+          wave_argmax(k, p2);
+          if (lane == 0) {
+            L.l2k[g] = k;
+            L.l2i[g] = p2;
+          }
+        }
+        for (int u = 0; u < per2; ++u) {
+          const int g = lane * per2 + u;
+          if (g < nt2) {
+            const double k = L.l2k[g];
+            if (k > bk) {
+              bk = k;
+              bp = L.l2i[g];
+            }
           }
         }
       }
@@ -1679,8 +1709,8 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
     ++flips;
     const double two = (s_new > 0) ? 2.0 : -2.0;
     // Update the neighbours.  A touched tile whose maximum was not among the
-    // updated magnets keeps that maximum unless an update beats it, so it
-    // needs no rescan: the largest new key of the tile is found with LDS
+    // updated magnets, or kept at least its key, keeps that maximum unless an
+    // update beats it, so it needs no rescan: the largest new key of the tile is found with LDS
     // atomics (positive doubles order like their bit patterns), then the
     // lowest index among the updates holding it.
     const bool incr = D <= 2 * NT;
@@ -1727,7 +1757,7 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
         const double ek = L.l1k[e];
         const uint32_t ei = L.l1i[e];
         L.l1flag[e] = 1;
-        if (!incr || (ek > 0.0 && (ei & 0x7fffffffu) == (uint32_t)i)) L.l1resc[e] = 1;
+        if (!incr || (ek > 0.0 && (ei & 0x7fffffffu) == (uint32_t)i && kk < ek)) L.l1resc[e] = 1;
         if (kk > 0.0) atomicMax(&L.l1nk[e], (unsigned long long)__double_as_longlong(kk));
         if (kk > tb_k) {
           tb_k = kk;
@@ -1749,17 +1779,27 @@ __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t
       const int ej = (int)(j >> l1s), gj = ej / kL2Group;
       double rk = 0.0;
       uint32_t rp = 0;
-      for (int u = 0; u < per2; ++u) {
-        const int g = lane * per2 + u;
-        if (g < nt2 && g != gj && L.l2k[g] > rk) {
-          rk = L.l2k[g];
-          rp = L.l2i[g];
+      if (flat) {
+        for (int u = 0; u < per1; ++u) {
+          const int e = lane * per1 + u;
+          if (e < nt1 && e != ej && L.l1k[e] > rk) {
+            rk = L.l1k[e];
+            rp = L.l1i[e];
+          }
         }
-      }
-      const int e = gj * kL2Group + lane;
-      if (e < nt1 && e != ej && L.l1k[e] > rk) {
-        rk = L.l1k[e];
-        rp = L.l1i[e];
+      } else {
+        for (int u = 0; u < per2; ++u) {
+          const int g = lane * per2 + u;
+          if (g < nt2 && g != gj && L.l2k[g] > rk) {
+            rk = L.l2k[g];
+            rp = L.l2i[g];
+          }
+        }
+        const int e = gj * kL2Group + lane;
+        if (e < nt1 && e != ej && L.l1k[e] > rk) {
+          rk = L.l1k[e];
+          rp = L.l1i[e];
+        }
       }
       wave_argmax(rk, rp);
       if (lane == 0)
@@ -1935,6 +1975,10 @@ __device__ __forceinline__ void rebuild_t1(const InstDev* __restrict__ I) {
 // max tree; a speculative step whose batches stay small continues on the
 // tree; a paused step resumes on the path it was on.  Both flip exactly the
 // magnets, in exactly the order, of the one-at-a-time relax.
+// kSpec false: the launch holds no instance that may speculate (every degree
+// above kSpecMaxD, or a workgroup below 1024 threads), so the kernel carries
+// the max tree alone and its registers are allocated for that path.
+template <bool kSpec>
 __device__ __forceinline__ int relax_step(const InstDev* __restrict__ I, RunDev* __restrict__ R, int64_t t,
                           unsigned char* lds_raw, RelaxShared& sh, SpecShared& ssh,
                           uint64_t deadline) {
@@ -1943,17 +1987,17 @@ __device__ __forceinline__ int relax_step(const InstDev* __restrict__ I, RunDev*
   int64_t flips = acc0;
   int64_t logpos = R->flips;
   uint64_t hash = R->hash;
-  bool spec = blockDim.x == 1024 &&
+  bool spec = kSpec && blockDim.x == 1024 &&
               (R->paused ? R->spec != 0 : (I->D <= kSpecMaxD && ncand >= I->spec_min));
   int status = 2;
   if ((int64_t)(uint32_t)ncand > I->ccap) {
     status = kPoolOverflow;  // cannot happen while every pass starts from an empty pool
   } else {
-    if (spec) status = relax_spec(I, t, lds_raw, ssh, ncand, flips, logpos, hash, deadline);
+    if (kSpec && spec) status = relax_spec(I, t, lds_raw, ssh, ncand, flips, logpos, hash, deadline);
     if (status == 2) {
-      if (spec) rebuild_t1(I);  // the keys have moved since the field phase
+      if (kSpec && spec) rebuild_t1(I);  // the keys have moved since the field phase
       spec = false;
-      status = relax_tree(I, t, lds_raw, sh, flips, logpos, hash, deadline);
+      status = relax_tree<!kSpec>(I, t, lds_raw, sh, flips, logpos, hash, deadline);
     }
   }
   __syncthreads();
@@ -1981,6 +2025,7 @@ __device__ __forceinline__ int relax_step(const InstDev* __restrict__ I, RunDev*
   return status;
 }
 
+template <bool kSpec>
 __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __restrict__ insts,
                                                               RunDev* __restrict__ runs) {
   RunDev* R = runs + blockIdx.x;
@@ -1990,7 +2035,7 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_relax(const InstDev* __
   extern __shared__ unsigned char lds_raw[];
   __shared__ RelaxShared sh;
   __shared__ SpecShared ssh;
-  relax_step(insts + blockIdx.x, R, R->t, lds_raw, sh, ssh, 0);
+  relax_step<kSpec>(insts + blockIdx.x, R, R->t, lds_raw, sh, ssh, 0);
 }
 
 // One workgroup per instance runs whole field steps -- its own field phase,
@@ -2033,7 +2078,7 @@ __global__ __launch_bounds__(64 * kMaxRelaxWaves) void k_fused(const InstDev* __
       __syncthreads();
     }
     ready = false;
-    if (relax_step(I, R, t, lds_raw, sh, ssh, deadline) != 0) break;
+    if (relax_step<true>(I, R, t, lds_raw, sh, ssh, deadline) != 0) break;
     if (threadIdx.x == 0) go = (R->active && !past(deadline)) ? 1 : 0;
     __syncthreads();
     if (!go) break;
@@ -2587,10 +2632,14 @@ void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, int32_t rows, 
 }
 
 void launch_relax(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
-                  size_t lds_bytes, hipStream_t st) {
+                  size_t lds_bytes, bool tree_only, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_relax, dim3((unsigned)count), dim3(64 * waves), lds_bytes, st, insts,
-                     runs);
+  if (tree_only)
+    hipLaunchKernelGGL(k_relax<false>, dim3((unsigned)count), dim3(64 * waves), lds_bytes, st,
+                       insts, runs);
+  else
+    hipLaunchKernelGGL(k_relax<true>, dim3((unsigned)count), dim3(64 * waves), lds_bytes, st,
+                       insts, runs);
 }
 
 void launch_fused(const InstDev* insts, RunDev* runs, int32_t count, int32_t waves,
@@ -2622,8 +2671,11 @@ size_t relax_lds_bytes(int64_t n, int32_t l1_shift) {
 hipError_t configure_kernels() {
   // the relax kernels take more than 64 KB of dynamic LDS
   const int bytes = (int)relax_lds_bytes((int64_t)kMaxL1Tiles << 6, 6);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_relax),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_relax<true>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_relax<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

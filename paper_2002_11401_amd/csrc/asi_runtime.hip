@@ -185,7 +185,8 @@ void relax_pass(asi_sim* s) {
     tp.kind = 1;
     (void)hipEventRecord(tp.a, s->stream);
   }
-  launch_relax(s->dI, s->dR, 1, s->relax_waves, s->lds, s->stream);
+  launch_relax(s->dI, s->dR, 1, s->relax_waves, s->lds, !relax_may_speculate(s->D, s->relax_waves),
+               s->stream);
   if (s->timing) {
     (void)hipEventRecord(tp.b, s->stream);
     s->timers.push_back(tp);
@@ -1463,6 +1464,7 @@ struct Table {
   int64_t nblocks = 0;
   int32_t waves = 1;
   size_t lds = 0;
+  bool tree_only = false;  // no instance of the table may speculate
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
 
@@ -1502,6 +1504,9 @@ asi_status table_build(Table& T, const std::vector<InstDev>& insts,
     int v = std::atoi(w);
     if (v >= 1 && v <= kMaxRelaxWaves) T.waves = v;
   }
+  T.tree_only = true;
+  for (int32_t k = 0; k < T.count; ++k)
+    if (insts[k].n > 0 && relax_may_speculate(insts[k].D, T.waves)) T.tree_only = false;
   T.nblocks = (int64_t)bi.size();
   T.dI = static_cast<InstDev*>(T.mem.alloc(sizeof(InstDev) * std::max(1, T.count)));
   T.dR = static_cast<RunDev*>(T.mem.alloc(sizeof(RunDev) * std::max(1, T.count)));
@@ -1525,7 +1530,7 @@ asi_status table_build(Table& T, const std::vector<InstDev>& insts,
 
 void table_step(Table& T, hipStream_t st) {
   launch_field(T.dI, T.dR, T.blk_inst, T.blk_row0, T.nblocks, st);
-  launch_relax(T.dI, T.dR, T.count, T.waves, T.lds, st);
+  launch_relax(T.dI, T.dR, T.count, T.waves, T.lds, T.tree_only, st);
 }
 
 asi_status table_capture(Table& T, hipStream_t st) {
@@ -1964,7 +1969,8 @@ asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out
     const int64_t ticks = std::max<int64_t>(1, (int64_t)(budget_ms * 1e-3 * (double)S->clock_hz));
     launch_field(S->T.dI, S->T.dR, S->T.blk_inst, S->T.blk_row0, S->T.nblocks, S->stream);
     if (quiet)
-      launch_relax(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, S->stream);
+      launch_relax(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, S->T.tree_only,
+                   S->stream);
     else
       launch_fused(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, tail ? 1 : INT64_MAX,
                    ticks, 1, S->stream);
@@ -1997,7 +2003,8 @@ asi_status asi_server_step(asi_server_t S, double budget_ms, int32_t* active_out
       const int64_t ticks = std::max<int64_t>(1, (int64_t)(left * (double)S->clock_hz));
       launch_field(S->T.dI, S->T.dR, S->T.blk_inst, S->T.blk_row0, S->T.nblocks, S->stream);
       if (quiet)
-        launch_relax(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, S->stream);
+        launch_relax(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, S->T.tree_only,
+                   S->stream);
       else
         launch_fused(S->T.dI, S->T.dR, S->T.count, S->T.waves, S->T.lds, 1, ticks, 1, S->stream);
       HIPCHK(hipMemcpyAsync(S->rb, S->T.dR, sizeof(RunDev) * S->max_slots,
