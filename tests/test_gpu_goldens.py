@@ -83,6 +83,30 @@ def test_batched_sweep_sample():
         s.close()
 
 
+def test_batched_sweep_sample_plain_runs():
+    """The same 16 sweep instances run one at a time (asi_run): degrees up to
+    128 take the relax kernel that holds both paths, the d = 10 instances
+    the max-tree-only kernel, whose root reads the first level directly up
+    to 512 tiles (9,660 and 14,280 magnets) and goes through the second level
+    above (74,112 and 77,224); each against the oracle's whole run."""
+    g = golden("batched_sweep_sample.json")
+    ws = W.batched_sweep(count=256, seed=4, n_steps=500)
+    kinds = set()
+    for k in sorted(g["instances"], key=int):
+        w = ws[int(k)]
+        s = asi.Sim.from_workload(w)
+        nt1 = -(-w.n // (1 << s.tuning()["l1_shift"]))
+        tree_only = s.info()["max_degree"] > 128
+        kind = ("tree only" if tree_only else "both paths",
+                "flat root" if tree_only and nt1 <= 512 else "two levels")
+        kinds.add(kind)
+        say("sweep instance", k, "plain", w.n, w.neighbor_distance, kind)
+        s.run()
+        check(s, g["instances"][k], f"sweep instance {k} (plain)")
+        s.close()
+    assert {("tree only", "flat root"), ("tree only", "two levels")} <= kinds, kinds
+
+
 def test_served_stream_sample():
     """64 jobs of the 2000-job stream (one per size stratum, the largest
     ~1M-magnet job included), submitted in arrival order to one server and
