@@ -1523,12 +1523,14 @@ __device__ __forceinline__ int relax_spec(const InstDev* __restrict__ I, int64_t
 // Relax one instance at step t with the whole workgroup (Sec. II.H).  The
 // flippable keys are kept in a three-level max tree: the key array in
 // memory, first-level tiles of 2^l1_shift magnets and second-level groups of
-// 64 tiles in LDS, built from the per-64-row maxima of the field phase.
+// 64 tiles in LDS, built from the per-64-row maxima of the field phase
+// (with kFlatOk, up to kFlatTiles tiles the root reads the tiles directly).
 // Per flip: the root gives j; thread 0 flips it and logs it; the threads
 // update j's neighbours (dipolar and total field += 2 s_new * coupling, new
-// key); the touched tiles and groups are rescanned.  Returns 0, -5 (flip
-// cap reached with a flippable magnet left) or 1 (deadline passed, checked
-// every 16 flips, with flippable magnets left).
+// key); the touched tiles are brought up to date from the updates, or
+// rescanned when their maximum fell, and then the touched groups.  Returns
+// 0, -5 (flip cap reached with a flippable magnet left) or 1 (deadline
+// passed, checked every 16 flips, with flippable magnets left).
 template <bool kFlatOk>
 __device__ __forceinline__ int relax_tree(const InstDev* __restrict__ I, int64_t t, unsigned char* lds_raw,
                           RelaxShared& sh, int64_t& flips, int64_t& logpos, uint64_t& hash,
