@@ -299,7 +299,8 @@ typedef struct {
   int32_t trials;       /* asi_tune: shapes timed (0: taken from the cache)  */
   int32_t field_rows;   /* rows per workgroup of the full-field pass at >= 128
                            neighbours (field_mode 2): 8, 16, 32 or 64; 0 =
-                           chosen by the instance size                      */
+                           chosen by the instance size (below 256 slices of
+                           64 rows: split over the 64-slot chunks)          */
 } asi_tuning;
 /* Autotuner: times the next sample_steps (>= 1, clipped to the protocol)
  * field steps under candidate shapes (rows per workgroup of the

@@ -91,6 +91,11 @@ struct InstDev {
   ASI_GLOBAL double* key;            // [n] Eq. 5 LHS if flippable, else 0
   ASI_GLOBAL double* t1key;          // [ceil(n/64)] per-64-row maximum key
   ASI_GLOBAL uint32_t* t1idx;        //   its index, bit 31 set when that spin is -1
+  // Per-chunk dipolar sums of the high-degree pass split over its 64-slot
+  // chunks: [nch][n] (easy, hard); null and nch == 0 when not allocated
+  ASI_GLOBAL double2* part;
+  int32_t nch;
+  int32_t pad1;
   ASI_GLOBAL int32_t* log_t;         // flip log
   ASI_GLOBAL int32_t* log_j;
   int64_t log_cap;
@@ -198,8 +203,17 @@ void launch_neighbour_fill(const double* x, const double* y, const double* mx, c
 // gathered) uses one workgroup per 64-row slice instead of one lane per row.
 constexpr int kHdMinD = 128;
 // Full-field pass of one instance of degree >= kHdMinD (field_mode full),
-// `rows` rows per workgroup (8, 16, 32 or 64; 0: chosen by the size).
-void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, int32_t rows, hipStream_t st);
+// `rows` rows per workgroup (8, 16, 32 or 64; 0: chosen by the size).  With
+// rows == 0, nch > 0 (the per-chunk sums allocated) and fewer than
+// kHdSplitSlices slices, the pass is split over the 64-slot chunks: a
+// workgroup per (slice, chunk), then a combine pass over the rows.
+void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, int32_t rows, int32_t nch,
+                     hipStream_t st);
+// Below this many 64-row slices the high-degree pass is split over chunks
+// (even 8 rows per workgroup then leave the device mostly idle while each
+// workgroup walks its chunks; above it the split's extra partial-sum
+// traffic and combine pass cost more than they save).
+constexpr int64_t kHdSplitSlices = 256;
 // Grid-wide field pass for every active instance of the table; rebuilds the
 // relax structures of every paused one.
 void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,

@@ -317,6 +317,11 @@ __global__ void k_nb_fill(const double* __restrict__ x, const double* __restrict
 __device__ __forceinline__ double field_finish(const InstDev* __restrict__ I, int64_t i, int64_t t,
                                                double p, double pq, uint32_t& payload);
 
+// Slots per chunk of the canonical dipolar sum (and of the high-degree
+// pass), and entries per thread per chunk in the high-degree pass.
+constexpr int kHdChunk = 64;
+constexpr int kHdPer = 8;
+
 __device__ __forceinline__ double field_row(const InstDev* __restrict__ I, int64_t i, int64_t t,
                                    uint32_t& payload) {
   const int8_t* __restrict__ s = I->s;
@@ -328,13 +333,19 @@ __device__ __forceinline__ double field_row(const InstDev* __restrict__ I, int64
     const int32_t* __restrict__ col = I->col + base;
     const double* __restrict__ A = I->A + base;
     const double* __restrict__ B = I->B + base;
-    // Chunks of 8 neighbours; the columns of the next chunk are fetched with
-    // the couplings and spins of the current one, so each chunk costs one
-    // round trip.  Accumulation stays in ascending neighbour order.  The
-    // tables are streamed once per pass (non-temporal loads), which leaves
-    // the L2 to the gathered spins.
+    // Groups of 8 neighbours; the columns of the next group are fetched
+    // with the couplings and spins of the current one, so each group costs
+    // one round trip.  The canonical order of the sum: each chunk of 64
+    // slots is added in ascending order from zero, and the chunk sums in
+    // ascending order (up to 64 neighbours, the plain left-to-right sum);
+    // every pass uses it, so all agree bit for bit.  The tables are streamed
+    // once per pass (non-temporal loads), which leaves the L2 to the
+    // gathered spins.
+    // (A chunk sum that ends on a 64-slot boundary is added there, the last
+    // one after the loop; a zero added after a full last chunk is exact.)
     p = 0.0;
     pq = 0.0;
+    double cp = 0.0, cq = 0.0;
     int32_t jc[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) jc[u] = (u < L) ? __builtin_nontemporal_load(&col[u * kSlice]) : 0;
@@ -353,11 +364,19 @@ __device__ __forceinline__ double field_row(const InstDev* __restrict__ I, int64
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         if (k + u < L) {
-          p += (sg[u] > 0) ? a[u] : -a[u];
-          pq += (sg[u] > 0) ? b[u] : -b[u];
+          cp += (sg[u] > 0) ? a[u] : -a[u];
+          cq += (sg[u] > 0) ? b[u] : -b[u];
         }
       }
+      if (((k + 8) & (kHdChunk - 1)) == 0) {
+        p += cp;
+        pq += cq;
+        cp = 0.0;
+        cq = 0.0;
+      }
     }
+    p += cp;
+    pq += cq;
     if (mode != kFieldFull) {
       I->hd[i] = make_double2(p, pq);
       I->dirty[i] = 0;
@@ -523,8 +542,6 @@ __global__ __launch_bounds__(kFieldBlock) void k_field(const InstDev* __restrict
 // same sums, in the same order, as field_row.  The workgroups of one slice
 // are launched on the same XCD (block ids that differ by multiples of 8),
 // so lines shared by two of them are fetched into one L2.
-constexpr int kHdChunk = 64;
-constexpr int kHdPer = 8;  // entries per thread per chunk
 
 template <int R>
 __global__ __launch_bounds__(8 * R) void k_field_hd(const InstDev* __restrict__ insts,
@@ -601,12 +618,16 @@ __global__ __launch_bounds__(8 * R) void k_field_hd(const InstDev* __restrict__ 
       const int k = k1 + kHdChunk + s0 + 8 * u;
       jc[u] = (k < L) ? __builtin_nontemporal_load(&I->col[base + (int64_t)k * 64]) : 0;
     }
-    if (tid < R) {
+    if (tid < R && k0 < L) {
+      // the chunk's sum from zero, then added to the row's (canonical order)
       const int kn = L - k0 < kHdChunk ? L - k0 : kHdChunk;
+      double cp = 0.0, cq = 0.0;
       for (int kk = 0; kk < kn; ++kk) {
-        p += sa[kk * R + tid];
-        pq += sb[kk * R + tid];
+        cp += sa[kk * R + tid];
+        cq += sb[kk * R + tid];
       }
+      p += cp;
+      pq += cq;
     }
     __syncthreads();
   }
@@ -627,6 +648,104 @@ __global__ __launch_bounds__(8 * R) void k_field_hd(const InstDev* __restrict__ 
   if (bal) {
     int pbase = 0;
     if (tid == 0) pbase = atomicAdd(I->ccount, __popcll(bal));
+    pbase = __builtin_amdgcn_readfirstlane(pbase);
+    pool_put(I, key, payload, bal, pbase);
+  }
+}
+
+// The high-degree pass split over the 64-slot chunks, for instances too
+// small to fill the device with k_field_hd (each of whose workgroups walks
+// its rows' chunks one round trip after another).  k_field_hd_part: a
+// 512-thread workgroup per (64-row slice, chunk) loads the chunk's slots of
+// its rows (eight per thread, couplings and columns together, then the
+// spins), stages the signed couplings in LDS, and the lane of each row adds
+// its chunk in ascending slot order from zero; the sums go to I->part.
+// k_field_hd_comb: a lane per row adds its chunk sums in ascending order --
+// the canonical order of every pass -- then finishes the row (Eq. 2, the
+// key), and each wavefront writes its 64 rows' maximum for the relax tree.
+__global__ __launch_bounds__(512) void k_field_hd_part(const InstDev* __restrict__ insts,
+                                                       RunDev* __restrict__ runs) {
+  __shared__ double sa[kHdChunk * 64];
+  __shared__ double sb[kHdChunk * 64];
+  if (!runs->active) return;
+  const InstDev* I = insts;
+  const int nch = I->nch;
+  const int64_t slice = blockIdx.x / nch;
+  const int g = (int)(blockIdx.x % nch);
+  const int64_t row0 = slice * 64;
+  if (row0 >= I->n) return;
+  const int tid = threadIdx.x;
+  const int r = tid & 63;   // the thread's row in the slice
+  const int s0 = tid >> 6;  // its first slot in the chunk; then every 8th
+  const int64_t i = row0 + r;
+  const int32_t L = (i < I->n) ? I->len[i] : 0;
+  const int64_t base = slot_of(row0, I->D, 0) + r;  // slot 0 of the thread's row
+  const int k0 = g * kHdChunk;
+  const int8_t* __restrict__ s = I->s;
+  int32_t jc[kHdPer];
+  double a[kHdPer], b[kHdPer];
+  int sg[kHdPer];
+#pragma unroll
+  for (int u = 0; u < kHdPer; ++u) {
+    const int k = k0 + s0 + 8 * u;
+    const bool ok = k < L;
+    jc[u] = ok ? __builtin_nontemporal_load(&I->col[base + (int64_t)k * 64]) : 0;
+    a[u] = ok ? __builtin_nontemporal_load(&I->A[base + (int64_t)k * 64]) : 0.0;
+    b[u] = ok ? __builtin_nontemporal_load(&I->B[base + (int64_t)k * 64]) : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kHdPer; ++u) sg[u] = (k0 + s0 + 8 * u < L) ? s[jc[u]] : 0;
+#pragma unroll
+  for (int u = 0; u < kHdPer; ++u) {
+    const int e = (s0 + 8 * u) * 64 + r;
+    sa[e] = (sg[u] > 0) ? a[u] : -a[u];
+    sb[e] = (sg[u] > 0) ? b[u] : -b[u];
+  }
+  __syncthreads();
+  if (tid < 64 && k0 < L) {
+    const int kn = L - k0 < kHdChunk ? L - k0 : kHdChunk;
+    double cp = 0.0, cq = 0.0;
+    for (int kk = 0; kk < kn; ++kk) {
+      cp += sa[kk * 64 + tid];
+      cq += sb[kk * 64 + tid];
+    }
+    I->part[(int64_t)g * I->n + i] = make_double2(cp, cq);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_field_hd_comb(const InstDev* __restrict__ insts,
+                                                       RunDev* __restrict__ runs) {
+  const RunDev* Rn = runs;
+  if (!Rn->active) return;
+  const InstDev* I = insts;
+  const int lane = threadIdx.x & 63;
+  const int64_t g64 = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t row0 = g64 << 6;
+  if (row0 >= I->n) return;
+  const int64_t i = row0 + lane;
+  uint32_t payload = 0;
+  double key = 0.0;
+  if (i < I->n) {
+    const int32_t L = I->len[i];
+    double p = 0.0, pq = 0.0;
+    for (int c = 0; c * kHdChunk < L; ++c) {
+      const double2 v = I->part[(int64_t)c * I->n + i];
+      p += v.x;
+      pq += v.y;
+    }
+    key = field_finish(I, i, Rn->t, p, pq, payload);
+  }
+  double mk = key;
+  uint32_t mp = payload;
+  wave_argmax(mk, mp);
+  if (lane == 0) {
+    I->t1key[g64] = mk;
+    I->t1idx[g64] = mp;
+  }
+  const unsigned long long bal = __ballot(key > 0.0);
+  if (bal) {
+    int pbase = 0;
+    if (lane == 0) pbase = atomicAdd(I->ccount, __popcll(bal));
     pbase = __builtin_amdgcn_readfirstlane(pbase);
     pool_put(I, key, payload, bal, pbase);
   }
@@ -2608,10 +2727,17 @@ void launch_field(const InstDev* insts, RunDev* runs, const int32_t* blk_inst,
                      blk_inst, blk_row0);
 }
 
-void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, int32_t rows, hipStream_t st) {
+void launch_field_hd(const InstDev* inst, RunDev* run, int64_t n, int32_t rows, int32_t nch,
+                     hipStream_t st) {
+  const int64_t nsl = (n + 63) / 64;
+  if (rows == 0 && nch > 0 && nsl < kHdSplitSlices) {
+    hipLaunchKernelGGL(k_field_hd_part, dim3((unsigned)(nsl * nch)), dim3(512), 0, st, inst, run);
+    hipLaunchKernelGGL(k_field_hd_comb, dim3((unsigned)((nsl + 3) / 4)), dim3(256), 0, st, inst,
+                       run);
+    return;
+  }
   // rows per workgroup: by default the largest that still gives the device
   // about four workgroups per compute unit, at least 8
-  const int64_t nsl = (n + 63) / 64;
   const int R = rows ? rows
                      : nsl >= 1024 ? 64 : 2 * nsl >= 1024 ? 32 : 4 * nsl >= 1024 ? 16 : 8;
   const unsigned blocks = (unsigned)(((nsl + 7) / 8) * 8 * (64 / R));

@@ -168,7 +168,7 @@ void field_pass(asi_sim* s) {
     (void)hipEventRecord(tp.a, s->stream);
   }
   if (s->hI.field_mode == kFieldFull && s->D >= kHdMinD)
-    launch_field_hd(s->dI, s->dR, s->n, s->field_rows, s->stream);
+    launch_field_hd(s->dI, s->dR, s->n, s->field_rows, s->hI.nch, s->stream);
   else
     launch_field(s->dI, s->dR, s->blk_inst, s->blk_row0, s->nblocks, s->stream);
   if (s->timing) {
@@ -273,6 +273,7 @@ size_t footprint_estimate(int64_t n, int64_t D, int64_t K, int64_t log_cap) {
   size_t b = slots * (4 + 8 + 8) + (size_t)n * (size_t)std::max<int64_t>(D, 1) * (4 + 8 + 8);
   b += (size_t)n * (4 + 8 + 8 + 8 + 1 + 1 + 8 * 7 + 4) + (size_t)(n + 8192) * 32;
   b += (size_t)nsl * 12 + (size_t)log_cap * 8 + (size_t)K * 20;
+  if (D >= kHdMinD && nsl < kHdSplitSlices) b += (size_t)n * (size_t)((D + 63) / 64) * 16;
   b += 1 << 16;
   return b;
 }
@@ -454,6 +455,15 @@ asi_status create_impl(const asi_params* p, const asi_device* dev, asi_sim* s) {
   I.key = dalloc<double>(s, n);
   I.t1key = dalloc<double>(s, nsl);
   I.t1idx = dalloc<uint32_t>(s, nsl);
+  // per-chunk sums of the high-degree pass, where it may be split over its
+  // chunks (a full-field instance of high degree and few slices)
+  I.part = nullptr;
+  I.nch = 0;
+  if (I.field_mode == kFieldFull && D >= kHdMinD && nsl < kHdSplitSlices) {
+    I.nch = (D + 63) / 64;
+    I.part = dalloc<double2>(s, (size_t)I.nch * (size_t)n);
+    if (!I.part) return fail(ASI_ENOMEM, "device allocation failed (chunk sums)");
+  }
   I.log_t = dalloc<int32_t>(s, log_cap);
   I.log_j = dalloc<int32_t>(s, log_cap);
   I.log_cap = log_cap;

@@ -1036,11 +1036,13 @@ def test_full_pass_and_dirty_row_modes_bitwise():  # noqa: D103
 @pytest.mark.parametrize("side,d", [(40, 10.0), (23, 7.0), (97, 7.0), (130, 5.0), (185, 5.0)])
 def test_high_degree_full_pass_bitwise(side, d):
     """At 128 or more neighbours the full-field pass runs a workgroup per 8,
-    16, 32 or 64 rows of a 64-row slice (by instance size: 3,280 and 1,104
-    magnets take 8 rows, 19,012 take 16, 34,060 take 32, 68,820 take 64; all
-    end in a ragged slice); its sums must equal the one-lane-per-row gather
-    bit for bit (dirty mode gathers every row at the first step and the rows
-    next to flips later), and the flips must match the oracle."""
+    16, 32 or 64 rows of a 64-row slice (by size: 3,280 and 1,104 magnets 8
+    rows, 19,012 16, 34,060 32, 68,820 64; all end in a ragged slice); below
+    256 slices (the two smallest) it is split by default into a workgroup per
+    (slice, 64-slot chunk) and a combine pass.  Split, unsplit and the one-lane-per-row
+    gather must give the same sums bit for bit (dirty mode gathers every row
+    at the first step and the rows next to flips later), and the flips must
+    match the oracle."""
     xy, theta = W.pinwheel_diamond(side)
     n = len(theta)
     H = W.linear_ramp(80, 0.1, -0.1, 30.0)
@@ -1049,21 +1051,26 @@ def test_high_degree_full_pass_bitwise(side, d):
                    b=0.38, c=1, beta=1.5, gamma=3.9, thermal_std=0.002, thermal_seed=6)
     a = gpu_sim(w, field_mode="full")
     b = gpu_sim(w, field_mode="dirty")
-    say("high-degree full pass", n, a.info()["max_degree"])
+    c = gpu_sim(w, field_mode="full")  # the unsplit pass, rows per workgroup by size
+    nsl = -(-n // 64)
+    rows = 64 if nsl >= 1024 else 32 if 2 * nsl >= 1024 else 16 if 4 * nsl >= 1024 else 8
+    tc = c.tuning()
+    c.set_tuning(tc["relax_waves"], tc["l1_shift"], tc["spec_min"], field_rows=rows)
+    say("high-degree full pass", n, a.info()["max_degree"], "split" if nsl < 256 else "unsplit",
+        "rows", rows)
     assert a.info()["max_degree"] >= 128
     for t in range(-1, 80, 20):
-        a.compute_fields(t)
-        b.compute_fields(t)
-        for x, y in zip(a.state()[:3], b.state()[:3]):
-            assert np.array_equal(x, y)
-    a.set_state(w.spin0, -1)
-    b.set_state(w.spin0, -1)
-    a.run()
-    b.run()
-    la, lb = a.flip_log(), b.flip_log()
-    assert la["hash"] == lb["hash"] and la["count"] == lb["count"] > 0
-    for x, y in zip(a.state()[:3], b.state()[:3]):
-        assert np.array_equal(x, y)
+        for s in (a, b, c):
+            s.compute_fields(t)
+        for x, y, z in zip(a.state()[:3], b.state()[:3], c.state()[:3]):
+            assert np.array_equal(x, y) and np.array_equal(x, z)
+    for s in (a, b, c):
+        s.set_state(w.spin0, -1)
+        s.run()
+    la, lb, lc = a.flip_log(), b.flip_log(), c.flip_log()
+    assert la["hash"] == lb["hash"] == lc["hash"] and la["count"] == lb["count"] == lc["count"] > 0
+    for x, y, z in zip(a.state()[:3], b.state()[:3], c.state()[:3]):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
     o, r = oracle_run(w)
     assert_same_flips(la, r, a.state()[0], o.spins())
 
